@@ -1,0 +1,526 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test checks the oracle against what the paper (arXiv:2406.15236) and
+the mathematics fix: an independent library routine, exact rational
+arithmetic, a closed form, a conservation law or a distribution.  None of
+them re-types the oracle's own formula.
+"""
+import math
+import os
+import shutil
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import stats
+from scipy.spatial.transform import Rotation
+
+import synth
+
+DEG = math.pi / 180.0
+
+
+# --------------------------------------------------------------------------
+# Random streams
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def rocrand_philox(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available for the rocRAND reference")
+    src = os.path.join(os.path.dirname(__file__), "philox_rocrand.cpp")
+    exe = str(tmp_path_factory.mktemp("rr") / "philox_rocrand")
+    subprocess.run([hipcc, "-O1", "-o", exe, src], check=True, capture_output=True)
+    return exe
+
+
+def test_philox_matches_rocrand(orc, rocrand_philox):
+    """Philox4x32-10 block function equals rocRAND's independent implementation."""
+    rng = np.random.default_rng(7)
+    rows = rng.integers(0, 2**32, size=(4000, 6), dtype=np.uint64)
+    rows[:8] = [[0, 0, 0, 0, 0, 0], [2**32 - 1] * 6, [0, 0, 0, 0, 2**32 - 1, 0],
+                [1, 0, 0, 0, 0, 0], [0, 1, 0, 0, 0, 0], [0, 0, 1, 0, 0, 0],
+                [0, 0, 0, 1, 0, 0], [5, 17, 100, 3, 1, 0]]
+    inp = "\n".join(" ".join(str(int(v)) for v in r) for r in rows) + "\n"
+    out = subprocess.run([rocrand_philox], input=inp, capture_output=True, text=True,
+                         check=True).stdout.split("\n")
+    for r, line in zip(rows, out):
+        ref = [int(v) for v in line.split()]
+        got = orc.philox(r[:4], r[4:])
+        assert list(got) == ref, (r, got, ref)
+
+
+def test_uniform_conversions(orc):
+    """Range, grid and end points of the word -> uniform conversions."""
+    assert orc.u24(0) == 0.0 and orc.u24(0xFFFFFFFF) == 1.0 - 2.0**-24
+    assert orc.u24(0xFF) == 0.0 and orc.u24(0x100) == 2.0**-24
+    assert orc.u53(0, 0) == 0.0 and orc.u53(0xFFFFFFFF, 0xFFFFFFFF) == 1.0 - 2.0**-53
+    assert orc.u53(0, 1 << 11) == 2.0**-53 and orc.u53(1, 0) == 2.0**-32
+    lo, hi = orc.u53_open(0, 0), orc.u53_open(0xFFFFFFFF, 0xFFFFFFFF)
+    assert 0.0 < lo and hi < 1.0 and lo + hi == 1.0
+    assert 0.0 < orc.u32_open(0) and orc.u32_open(0xFFFFFFFF) < 1.0
+    assert orc.u32_open(0) + orc.u32_open(0xFFFFFFFF) == 1.0
+    rng = np.random.default_rng(3)
+    for a, b in rng.integers(0, 2**32, size=(200, 2)):
+        u = orc.u53(int(a), int(b))
+        assert 0.0 <= u < 1.0 and Fraction(u) * 2**53 == int(Fraction(u) * 2**53)
+
+
+def test_shift_grid_and_uniformity(orc):
+    """Sec. II: one random lattice shift per step, uniform in [-a/2, a/2)^3."""
+    p = orc.Params(seed=11)
+    s = np.array([orc.shift(p, t) for t in range(4000)])
+    assert s.min() >= -0.5 and s.max() < 0.5
+    assert np.all(s * 2**24 == np.round(s * 2**24))  # exact 2^-24 grid
+    for k in range(3):
+        assert stats.kstest(s[:, k], stats.uniform(-0.5, 1.0).cdf).pvalue > 1e-3
+    assert abs(np.corrcoef(s[:-1, 0], s[1:, 0])[0, 1]) < 0.06
+    assert not np.array_equal(orc.shift(p, 5), orc.shift(orc.Params(seed=12), 5))
+
+
+# --------------------------------------------------------------------------
+# Streaming, Eq.(1)
+# --------------------------------------------------------------------------
+def _wrapped_exact(x, h, v, L):
+    """x + h v in exact rational arithmetic, then brought into [0, L)."""
+    e = Fraction(x) + Fraction(h) * Fraction(v)
+    while e < 0:
+        e += L
+    while e >= L:
+        e -= L
+    return e
+
+
+def test_stream_exact_single_rounding(orc):
+    """Eq.(1): r <- r + h v with one rounding (fma) and periodic images."""
+    L = (16, 8, 12)
+    p = orc.Params(L=L, h=0.1)
+    x, v = synth.box_state(L, n=3000, seed=5)
+    v[:, :50] *= 30.0  # some particles cross the boundary
+    x2, v2, nb = orc.stream(p, x, v)
+    assert nb == 0 and np.array_equal(v2, v)
+    for k in range(3):
+        for i in range(x.shape[1]):
+            ex = _wrapped_exact(x[k, i], p.h, v[k, i], L[k])
+            e_unwrapped = Fraction(x[k, i]) + Fraction(p.h) * Fraction(v[k, i])
+            got = Fraction(x2[k, i])
+            assert 0 <= x2[k, i] < L[k]
+            if 0 <= e_unwrapped < L[k]:
+                assert x2[k, i] == float(e_unwrapped)  # correctly rounded, one rounding
+            else:
+                assert abs(got - ex) <= Fraction(2.0**-52) * L[k] or abs(got - ex) >= L[k] - 1e-9
+
+
+def test_stream_wrap_corner(orc):
+    """A particle landing a hair below 0 maps into [0, L), never onto L."""
+    p = orc.Params(L=(4, 4, 4), h=1.0)
+    x = np.array([[1e-18, 3.5, 0.0], [0.5, 0.5, 0.5], [0.5, 0.5, 0.5]])
+    v = np.array([[-2e-18, 0.5, -0.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    x2, _, _ = orc.stream(p, x, v)
+    assert np.all(x2 >= 0) and np.all(x2 < 4)
+    assert x2[0, 0] == 0.0          # 4 - 1e-18 rounds to 4 -> corner rule gives 0
+    assert x2[0, 1] == 0.0          # 3.5 + 0.5 == L exactly -> 0
+
+
+def test_bounce_back_walls(orc):
+    """No-slip walls: particles crossing z=0 or z=H are mirrored back onto the
+    fluid side with all velocity components reversed; time reversal restores
+    the start (Sec. II, Boundary conditions)."""
+    L = (8, 8, 6)
+    p = orc.Params(L=L, h=0.5, walls=True)
+    x, v = synth.box_state(L, n=5000, seed=9)
+    v *= 3.0
+    x2, v2, nb = orc.stream(p, x, v)
+    zend = x[2] + p.h * v[2]
+    crossed = (zend < 0) | (zend > L[2])
+    assert nb == int(crossed.sum()) > 100
+    assert np.all((x2[2] >= 0) & (x2[2] <= L[2]))
+    assert np.array_equal(v2[:, crossed], -v[:, crossed])
+    assert np.array_equal(v2[:, ~crossed], v[:, ~crossed])
+    bot = crossed & (zend < 0)
+    top = crossed & (zend > L[2])
+    np.testing.assert_allclose(x2[2, bot], -zend[bot], atol=1e-13)
+    np.testing.assert_allclose(x2[2, top], 2 * L[2] - zend[top], atol=1e-13)
+    # x, y: the particle travels the reflected path, r_end - 2 v t_rem
+    trem = np.where(bot, zend / v[2], (zend - L[2]) / v[2])
+    for k in range(2):
+        exp = (x[k] + p.h * v[k] - 2 * v[k] * trem) % L[k]
+        d = np.abs(x2[k, crossed] - exp[crossed])
+        assert np.all(np.minimum(d, L[k] - d) < 1e-12)
+    # time reversal: stream back with reversed velocities
+    x3, v3, _ = orc.stream(p, x2, -v2)
+    for k in range(3):
+        d = np.abs(x3[k] - x[k])
+        if k < 2:
+            d = np.minimum(d, L[k] - d)
+        assert d.max() < 1e-12
+    np.testing.assert_array_equal(-v3, v)
+
+
+# --------------------------------------------------------------------------
+# Binning
+# --------------------------------------------------------------------------
+def _exact_key(xi, s, L, walls):
+    c = [math.floor(Fraction(float(xi[k])) + Fraction(float(s[k]))) for k in range(3)]
+    c[0] %= L[0]
+    c[1] %= L[1]
+    if walls:
+        c[2] += 1
+        dims = (L[2] + 2, L[1], L[0])
+    else:
+        c[2] %= L[2]
+        dims = (L[2], L[1], L[0])
+    return int(np.ravel_multi_index((c[2], c[1], c[0]), dims))
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_keys_exact_floor(orc, walls):
+    """key = linear index (x fastest) of floor(x + s) mod L, by exact arithmetic,
+    including particles placed exactly on shifted cell faces."""
+    L = (7, 5, 6)
+    p = orc.Params(L=L, walls=walls, seed=21)
+    rng = np.random.default_rng(2)
+    for t in range(6):
+        s = orc.shift(p, t)
+        x, _ = synth.box_state(L, n=800, seed=100 + t)
+        # faces: x = j - s (exactly representable), and the box ends
+        for k in range(3):
+            j = rng.integers(0, L[k] + 1, size=60)
+            face = j.astype(float) - s[k]
+            ok = (face >= 0) & (face < L[k])
+            x[k, :60] = np.where(ok, face, x[k, :60])
+        x[:, 60] = 0.0
+        x[:, 61] = [np.nextafter(L[0], 0), np.nextafter(L[1], 0), np.nextafter(L[2], 0)]
+        key = orc.keys(p, t, x)
+        ref = [_exact_key(x[:, i], s, L, walls) for i in range(x.shape[1])]
+        assert list(key) == ref
+
+
+def test_counting_sort_matches_numpy(orc):
+    """Stable counting sort == numpy stable argsort, offsets == cumsum(bincount)."""
+    rng = np.random.default_rng(4)
+    for ncell, n in [(1, 0), (1, 7), (64, 1000), (4096, 40960), (1000, 3)]:
+        key = rng.integers(0, ncell, size=n).astype(np.uint32)
+        perm, off = orc.sort(key, ncell)
+        np.testing.assert_array_equal(perm, np.argsort(key, kind="stable"))
+        ref = np.concatenate([[0], np.cumsum(np.bincount(key, minlength=ncell))])
+        np.testing.assert_array_equal(off, ref)
+
+
+# --------------------------------------------------------------------------
+# Collision, Eq.(2), and the MBS thermostat
+# --------------------------------------------------------------------------
+def _one_step_parts(orc, p, t, x, v):
+    xs, vs, _ = orc.stream(p, x, v)
+    key = orc.keys(p, t, xs)
+    perm, off = orc.sort(key, p.ncells)
+    v2, cells = orc.collide(p, t, vs, perm, off, cells=True)
+    return xs, vs, key, perm, off, v2, cells
+
+
+def test_rotation_matches_scipy(orc):
+    """Rodrigues rotation == scipy Rotation.from_rotvec(alpha n).apply(u)."""
+    rng = np.random.default_rng(8)
+    for _ in range(500):
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        u = rng.normal(size=3)
+        a = rng.uniform(0, 2 * math.pi)
+        ref = Rotation.from_rotvec(a * n).apply(u)
+        np.testing.assert_allclose(orc.rotate(a, n, u), ref, rtol=0, atol=1e-14)
+    n = np.array([0.0, 0.0, 1.0])
+    np.testing.assert_allclose(orc.rotate(math.pi / 2, n, [1.0, 0, 0]), [0, 1, 0], atol=1e-16)
+
+
+def test_cell_sums_against_fsum(orc):
+    """Cell mean velocity and relative kinetic term vs correctly rounded sums."""
+    L = (6, 6, 6)
+    p = orc.Params(L=L, mbs=True, seed=3)
+    x, v = synth.box_state(L, seed=31)
+    xs, vs, key, perm, off, v2, cells = _one_step_parts(orc, p, 0, x, v)
+    for c in range(p.ncells):
+        idx = np.nonzero(key == c)[0]
+        if idx.size == 0:
+            continue
+        assert cells[c, 0] == idx.size
+        Vex = [math.fsum(vs[k, idx]) / idx.size for k in range(3)]
+        np.testing.assert_allclose(cells[c, 2:5], Vex, rtol=0, atol=4e-16 * max(1, idx.size))
+        Kex = math.fsum(((vs[:, idx] - np.array(Vex)[:, None]) ** 2).ravel())
+        assert abs(cells[c, 5] - Kex) <= 1e-13 * max(Kex, 1e-300) + 1e-15
+
+
+@pytest.mark.parametrize("mbs", [False, True])
+def test_collision_is_rotation_of_relative_velocity(orc, mbs):
+    """Eq.(2): v' - v_cm = kappa * R(alpha, n)(v - v_cm) per particle, with R from
+    scipy and the cell's axis; kappa = 1 without the thermostat."""
+    L = (5, 6, 4)
+    p = orc.Params(L=L, mbs=mbs, seed=17, alpha=1.9)
+    x, v = synth.box_state(L, seed=41)
+    xs, vs, key, perm, off, v2, cells = _one_step_parts(orc, p, 3, x, v)
+    for c in range(p.ncells):
+        idx = np.nonzero(key == c)[0]
+        if idx.size < 2:
+            np.testing.assert_array_equal(v2[:, idx], vs[:, idx])  # unchanged
+            continue
+        V = cells[c, 2:5]
+        n = cells[c, 6:9]
+        assert abs(np.linalg.norm(n) - 1) < 1e-15
+        kappa = cells[c, 9]
+        if not mbs:
+            assert kappa == 1.0
+        R = Rotation.from_rotvec(p.alpha * n)
+        ref = V[:, None] + kappa * R.apply((vs[:, idx] - V[:, None]).T).T
+        np.testing.assert_allclose(v2[:, idx], ref, rtol=0, atol=1e-14)
+
+
+def test_per_cell_momentum_and_energy_conservation(orc):
+    """Sec. II: the collision conserves momentum per cell, and without the
+    thermostat also kinetic energy per cell."""
+    L = (8, 8, 8)
+    p = orc.Params(L=L, seed=5)
+    x, v = synth.box_state(L, seed=51)
+    xs, vs, key, perm, off, v2, cells = _one_step_parts(orc, p, 7, x, v)
+    for c in range(p.ncells):
+        idx = np.nonzero(key == c)[0]
+        if idx.size == 0:
+            continue
+        scale = np.abs(vs[:, idx]).sum()
+        dP = np.abs(v2[:, idx].sum(axis=1) - vs[:, idx].sum(axis=1)).max()
+        assert dP <= 8 * 2.2e-16 * scale * max(1, idx.size)
+        E0, E1 = (vs[:, idx] ** 2).sum(), (v2[:, idx] ** 2).sum()
+        assert abs(E1 - E0) <= 1e-14 * E0 + 1e-300
+
+
+def test_special_angles(orc):
+    """alpha = 0 leaves v unchanged; alpha = pi gives u' = 2 (n.u) n - u."""
+    L = (4, 4, 4)
+    x, v = synth.box_state(L, seed=61)
+    for alpha in (0.0, math.pi):
+        p = orc.Params(L=L, alpha=alpha, seed=2)
+        xs, vs, key, perm, off, v2, cells = _one_step_parts(orc, p, 1, x, v)
+        for c in range(p.ncells):
+            idx = np.nonzero(key == c)[0]
+            if idx.size < 2:
+                continue
+            V, n = cells[c, 2:5], cells[c, 6:9]
+            u = vs[:, idx] - V[:, None]
+            ref = u if alpha == 0.0 else 2 * (n @ u) * n[:, None] - u
+            np.testing.assert_allclose(v2[:, idx] - V[:, None], ref, atol=2e-15)
+
+
+def test_axis_uniform_on_sphere(orc):
+    """Sec. II: the rotation axis is random and independent per cell and step."""
+    p = orc.Params(seed=9)
+    n = np.array([orc.cell_axis(p, t, c) for t in range(5) for c in range(1200)])
+    np.testing.assert_allclose(np.linalg.norm(n, axis=1), 1.0, atol=2e-16)
+    assert stats.kstest(n[:, 2], stats.uniform(-1, 2).cdf).pvalue > 1e-3
+    phi = np.arctan2(n[:, 1], n[:, 0])
+    assert stats.kstest(phi, stats.uniform(-math.pi, 2 * math.pi).cdf).pvalue > 1e-3
+    assert np.abs(n.mean(axis=0)).max() < 0.05
+    assert not np.allclose(orc.cell_axis(p, 0, 3), orc.cell_axis(p, 1, 3))
+
+
+@pytest.mark.parametrize("shape", [1.5, 3.0, 13.5, 28.5])
+def test_gamma_sampler_distribution(orc, shape):
+    """Sec. II (Thermostat): E_k ~ Gamma(f/2, kT); Marsaglia-Tsang sampler vs scipy."""
+    p = orc.Params(seed=77)
+    g = np.empty(6000)
+    att = np.empty(6000, dtype=int)
+    for i in range(g.size):
+        g[i], att[i] = orc.cell_gamma(p, i // 1000, i % 1000, shape)
+    assert att.min() >= 1 and att.mean() < 1.2
+    assert stats.kstest(g, stats.gamma(shape).cdf).pvalue > 1e-3
+    assert abs(g.mean() / shape - 1) < 4 * math.sqrt(1 / (shape * g.size)) + 1e-3
+
+
+def test_mbs_sets_cell_energy_to_drawn_value(orc):
+    """MBS: after the collision the relative kinetic energy of each cell equals
+    the drawn E_k, whose law is Gamma(3(N_c-1)/2, kT)."""
+    L = (10, 10, 10)
+    p = orc.Params(L=L, mbs=True, kT=1.7, seed=13)
+    x, v = synth.box_state(L, seed=71, kT=0.6)
+    xs, vs, key, perm, off, v2, cells = _one_step_parts(orc, p, 2, x, v)
+    sel = cells[:, 0] >= 2
+    Ek, Kpost = cells[sel, 10], cells[sel, 15]
+    np.testing.assert_allclose(Kpost, 2 * Ek, rtol=1e-12)
+    n = cells[sel, 0]
+    z = Ek / p.kT
+    shape = 1.5 * (n - 1)
+    u = stats.gamma.cdf(z, shape)  # probability integral transform
+    assert stats.kstest(u, "uniform").pvalue > 1e-3
+
+
+def test_mbs_thermalises(orc):
+    """With MBS the temperature relaxes to kT from a hotter start."""
+    L = (8, 8, 8)
+    p = orc.Params(L=L, mbs=True, kT=1.0, seed=23)
+    x, v = synth.box_state(L, kT=2.5, seed=81)
+    x, v = orc.run(p, x, v, 20)
+    T = orc.observables(p, v)["T"]
+    assert abs(T - 1.0) < 0.03
+
+
+def test_storage_order_invariance(orc):
+    """The step does not depend on how particles are stored."""
+    L = (6, 5, 7)
+    p = orc.Params(L=L, mbs=True, seed=29)
+    x, v = synth.box_state(L, seed=91)
+    q = np.random.default_rng(0).permutation(x.shape[1])
+    xa, va = orc.step(p, 4, x, v)
+    xb, vb = orc.step(p, 4, x[:, q], v[:, q])
+    np.testing.assert_array_equal(xb, xa[:, q])
+    np.testing.assert_allclose(vb, va[:, q], rtol=0, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Phantom particles
+# --------------------------------------------------------------------------
+def _fraction_in_wall(cz, sz, H):
+    """Length of the layer [cz - sz, cz + 1 - sz) lying outside [0, H]."""
+    lo, hi = cz - sz, cz + 1 - sz
+    inside = max(0.0, min(hi, H) - max(lo, 0.0))
+    return 1.0 - inside
+
+
+def test_wall_fraction_geometry(orc):
+    """Wall volume fraction of each shifted layer, by interval intersection."""
+    H = 9
+    p = orc.Params(L=(4, 4, H), walls=True)
+    for sz in [-0.5, -0.31, -2.0**-24, 0.0, 2.0**-24, 0.25, 0.5 - 2.0**-24]:
+        for cz in range(-1, H + 1):
+            exp = _fraction_in_wall(cz, sz, H)
+            got = orc.wall_fraction(p, sz, cz)
+            if exp >= 1.0 - 1e-15 and got == 0.0:
+                continue  # layer entirely inside the wall holds no fluid
+            assert abs(got - exp) < 1e-15, (sz, cz, got, exp)
+
+
+def test_phantom_count_and_velocity_laws(orc):
+    """Phantoms: count Poisson(<N_c> f_w), velocities N(0, kT/m) per component."""
+    p = orc.Params(density=10.0, kT=2.0, mass=1.0, walls=True, seed=3)
+    fw = 0.37
+    counts, vel = [], []
+    for i in range(4000):
+        ph = orc.phantoms(p, i // 500, i % 500, fw)
+        counts.append(len(ph))
+        vel.append(ph)
+    counts = np.array(counts)
+    lam = p.density * fw
+    ks = np.arange(0, counts.max() + 1)
+    obs = np.bincount(counts, minlength=ks.size)
+    exp = stats.poisson.pmf(ks, lam) * counts.size
+    keep = exp > 5
+    chi2 = ((obs[keep] - exp[keep]) ** 2 / exp[keep]).sum()
+    assert stats.chi2.sf(chi2, keep.sum() - 1) > 1e-3
+    allv = np.concatenate(vel).ravel()
+    assert stats.kstest(allv, stats.norm(0, math.sqrt(p.kT / p.mass)).cdf).pvalue > 1e-3
+
+
+# --------------------------------------------------------------------------
+# Many steps: Maxwell distribution, conservation, observables
+# --------------------------------------------------------------------------
+def test_maxwell_from_non_gaussian_start(orc):
+    """SRD drives any velocity distribution to Maxwell-Boltzmann at the
+    temperature fixed by the (conserved) energy."""
+    L = (8, 8, 8)
+    p = orc.Params(L=L, seed=37)
+    x, v = synth.box_state(L, seed=7, velocity="uniform")
+    assert abs(stats.kurtosis(v.ravel(), fisher=False) - 1.8) < 0.05
+    x, v = orc.run(p, x, v, 200)
+    T = orc.observables(p, v)["T"]
+    w = (v - v.mean(axis=1, keepdims=True)).ravel()
+    assert stats.kstest(w, stats.norm(0, math.sqrt(T)).cdf).pvalue > 1e-3
+    kurt = stats.kurtosis(w, fisher=False)
+    assert abs(kurt - 3.0) < 4 * math.sqrt(24.0 / w.size)
+
+
+def test_energy_and_momentum_conservation_100_steps(orc):
+    """Without the thermostat SRD conserves energy and momentum over many steps."""
+    L = (8, 8, 8)
+    p = orc.Params(L=L, seed=41)
+    x, v = synth.box_state(L, seed=17)
+    o0 = orc.observables(p, v)
+    x, v = orc.run(p, x, v, 100, reorder_every=7)
+    o1 = orc.observables(p, v)
+    assert abs(o1["E"] - o0["E"]) / o0["E"] < 1e-12
+    assert np.abs(o1["P"] - o0["P"]).max() < 1e-10 * math.sqrt(x.shape[1])
+    assert o1["N"] == x.shape[1]
+
+
+def test_observables_against_fsum(orc):
+    L = (5, 5, 5)
+    p = orc.Params(L=L, mass=1.5)
+    _, v = synth.box_state(L, seed=3)
+    v = v + 0.3
+    o = orc.observables(p, v)
+    for k in range(3):
+        assert o["P"][k] == pytest.approx(1.5 * math.fsum(v[k]), abs=1e-12)
+    assert o["E"] == pytest.approx(0.75 * math.fsum((v ** 2).ravel()), rel=1e-14)
+    dv = v - v.mean(axis=1, keepdims=True)
+    T = 1.5 * math.fsum((dv ** 2).ravel()) / (3 * (v.shape[1] - 1))
+    assert o["T"] == pytest.approx(T, rel=1e-13)
+
+
+def test_reorder_is_gather(orc):
+    rng = np.random.default_rng(1)
+    x, v = rng.normal(size=(3, 50)), rng.normal(size=(3, 50))
+    perm = rng.permutation(50).astype(np.uint32)
+    x2, v2 = orc.reorder(x, v, perm)
+    np.testing.assert_array_equal(x2, x[:, perm])
+    np.testing.assert_array_equal(v2, v[:, perm])
+
+
+def test_step_is_composition_of_parts(orc):
+    L = (6, 6, 6)
+    p = orc.Params(L=L, mbs=True, seed=43)
+    x, v = synth.box_state(L, seed=19)
+    xs, vs, key, perm, off, v2, _ = _one_step_parts(orc, p, 9, x, v)
+    xa, va, ka, pa, oa = orc.step(p, 9, x, v, reorder=True, binning=True)
+    np.testing.assert_array_equal(ka, key)
+    np.testing.assert_array_equal(pa, perm)
+    np.testing.assert_array_equal(oa, off)
+    np.testing.assert_array_equal(xa, xs[:, perm])
+    np.testing.assert_array_equal(va, v2[:, perm])
+
+
+# --------------------------------------------------------------------------
+# Poiseuille flow: walls + phantoms + gravity + thermostat together
+# --------------------------------------------------------------------------
+def srd_viscosity(nc, h, alpha, kT=1.0, m=1.0):
+    """Kinetic + collisional SRD viscosity with random shift (literature form)."""
+    e = nc - 1 + math.exp(-nc)
+    kin = nc * kT * h * (5 * nc / (e * (4 - 2 * math.cos(alpha) - 2 * math.cos(2 * alpha))) - 0.5)
+    col = m / (18 * h) * e * (1 - math.cos(alpha))
+    return kin + col
+
+
+@pytest.mark.slow
+def test_poiseuille_profile(orc):
+    """Gravity along x between no-slip walls gives the parabola
+    v_x(z) = rho g z (H - z) / (2 eta) (Sec. II, External fields)."""
+    L = (8, 8, 16)
+    H = L[2]
+    g = 0.01
+    p = orc.Params(L=L, walls=True, mbs=True, g=(g, 0.0, 0.0), seed=5)
+    x, v = synth.box_state(L, seed=13)
+    x, v = orc.run(p, x, v, 1500)
+    nb = 32
+    acc = np.zeros(nb)
+    cnt = np.zeros(nb)
+    for t in range(1500, 3000):
+        x, v = orc.step(p, t, x, v)
+        b = np.minimum((x[2] / H * nb).astype(int), nb - 1)
+        acc += np.bincount(b, weights=v[0], minlength=nb)
+        cnt += np.bincount(b, minlength=nb)
+    prof = acc / cnt
+    z = (np.arange(nb) + 0.5) * H / nb
+    A = np.vstack([z * (H - z), np.ones(nb)]).T
+    (a, c), *_ = np.linalg.lstsq(A, prof, rcond=None)
+    vmax = a * H * H / 4
+    eta_fit = p.density * g / (2 * a)
+    eta_th = srd_viscosity(p.density, p.h, p.alpha)
+    assert abs(c) < 0.05 * vmax            # no slip at the walls
+    assert abs(eta_fit / eta_th - 1) < 0.10
+    resid = prof - A @ np.array([a, c])
+    assert np.abs(resid).max() < 0.05 * vmax
