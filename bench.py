@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Throughput of the MPC-SRD step on one MI355X.
+
+Prints ONE JSON line.  `value` is FP64 particle-steps/s on the 256^3 periodic
+box with the Maxwell-Boltzmann-scaling thermostat, 10 particles per cell and
+particles reordered by cell every 20 steps (inputs resident in HBM before the
+timed region).  The same line carries:
+  roofline     : the collide kernel (dominant) -- algorithmic bytes per launch
+                 (particles x state bytes read + written once) / its average
+                 duration from HIP events on the launch stream;
+  forms        : FP32 and split-FP32 on the same box, and the batched
+                 ensemble of 64 uneven boxes (graph replay);
+  cpu_baseline : the single-threaded CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0                       # MI355X HBM3E peak, GB/s
+STATE_BYTES = {"fp64": 48, "fp32": 24, "split": 28}   # stored bytes per particle
+METRIC = "MPC particle-steps/s on 1 GPU + % HBM roofline, FP64 vs split-FP32 vs batched"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("mpc_kernels.hip", "mpc_internal.h", "philox_dev.h"):
+        with open(os.path.join(ROOT, "paper_2406_15236_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(form: str, workload: str):
+    """HBM bytes per collide launch from committed rocprofv3 counter runs, if
+    they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "collide_hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except OSError:
+        return None
+    r = rec.get(f"{workload}:{form}")
+    if not r or r.get("kernel_hash") != kernel_source_hash():
+        return None
+    return r
+
+
+def run_box(mpc, torch, box: dict, form: str, R: int, steps: int, warmup: int,
+            profiled: bool = True):
+    sim = mpc.Sim(box if isinstance(box, list) else [box], form=form, reorder_every=R,
+                  graph=not profiled)
+    sim.init_state(2024)
+    n = sum(sim.n(b) for b in range(len(sim.params)))
+    if warmup:
+        sim.step(warmup) if not profiled else sim.step_profiled(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if profiled:
+        kt = sim.step_profiled(steps)
+    else:
+        sim.step(steps)
+        kt = None
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.sync()
+    obs = sim.observables(0)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return n, wall, kt, obs
+
+
+def cpu_baseline(seconds_hint: float = 15.0):
+    """Single-threaded FP64 oracle on a 128^3 sample of the 256^3 workload."""
+    import oracle
+    import synth
+    box = synth.config("C2")
+    L = (128, 128, 128)
+    p = oracle.Params(L=L, h=box["h"], alpha=box["alpha"], kT=1.0, density=10.0, seed=1,
+                      mbs=True)
+    x, v = synth.box_state(L, seed=1)
+    n = x.shape[1]
+    oracle.step(p, 0, x, v)   # warm
+    steps = 0
+    t0 = time.perf_counter()
+    t = 1
+    while True:
+        x, v = oracle.step(p, t, x, v, reorder=((t + 1) % 20 == 0))
+        steps += 1
+        t += 1
+        if time.perf_counter() - t0 > seconds_hint or steps >= 6:
+            break
+    wall = time.perf_counter() - t0
+    return {"value": n * steps / wall, "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"128^3 cells x 10/cell ({n} particles), MBS, {steps} steps, "
+                      "1 thread (1/8 of the 256^3 workload's cells)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--forms", default="fp32,split,batched",
+                    help="extra entries besides the FP64 headline (comma list, or none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=500)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU path is a design in DESIGN.md, not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2406_15236_amd as mpc
+    import synth
+    mpc.lib()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    box = synth.config("C2")
+    workload = "C2"
+    n, wall, kt, obs = run_box(mpc, torch, box, "fp64", 20, args.steps, args.warmup)
+    value = n * args.steps / wall
+    ms_step = wall * 1e3 / args.steps
+    coll_ms = kt.collide_ms / max(1, kt.collide_launches)
+    alg_bytes = n * 2 * STATE_BYTES["fp64"]
+    achieved = alg_bytes / (coll_ms * 1e-3) / 1e9
+    tr = traffic_record("fp64", workload)
+    print(f"[fp64 C2] N={n} {ms_step:.3f} ms/step: scan {kt.scan_ms / args.steps:.3f} "
+          f"scatter {kt.scatter_ms / args.steps:.3f} collide {coll_ms:.3f} "
+          f"other {kt.other_ms / args.steps:.3f} ms; T={obs['T']:.4f}", file=sys.stderr)
+    line = {
+        "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "256^3 periodic cells, 10 particles/cell "
+                               f"({n} particles), MBS thermostat, kT=1, h=0.1, "
+                               "alpha=130deg, FP64 SoA, reorder every 20 steps",
+                   "particles": n, "cells": 256 ** 3},
+        "hbm_roofline_frac_step": value * 2 * STATE_BYTES["fp64"] / (HBM_PEAK_GBS * 1e9),
+        "roofline": {"bound": "hbm", "kernel": "k_collide<fp64>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": tr["bytes_per_launch"] if tr else None,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "avg_launch_ms": coll_ms},
+        "kernels_ms_per_step": {"scan": kt.scan_ms / args.steps,
+                                "scatter": kt.scatter_ms / args.steps,
+                                "collide": coll_ms, "advance": kt.other_ms / args.steps},
+    }
+    forms = {}
+    extra = [f for f in args.forms.split(",") if f and f != "none"]
+    for form in extra:
+        try:
+            if form in ("fp32", "split"):
+                n2, w2, k2, o2 = run_box(mpc, torch, box, form, 20, args.steps, args.warmup)
+                v2 = n2 * args.steps / w2
+                c2 = k2.collide_ms / max(1, k2.collide_launches)
+                forms[form] = {
+                    "workload": "same 256^3 box", "value": v2, "unit": "particle-steps/s",
+                    "ms_per_step": w2 * 1e3 / args.steps,
+                    "hbm_roofline_frac_step": v2 * 2 * STATE_BYTES[form] / (HBM_PEAK_GBS * 1e9),
+                    "collide_ms": c2,
+                    "collide_achieved_GBs": n2 * 2 * STATE_BYTES[form] / (c2 * 1e-3) / 1e9}
+                print(f"[{form} C2] {w2 * 1e3 / args.steps:.3f} ms/step collide {c2:.3f} ms",
+                      file=sys.stderr)
+            elif form == "batched":
+                boxes = synth.batch_boxes(64, seed=4)
+                nb, wb, _, _ = run_box(mpc, torch, boxes, "fp64", 0, args.batched_steps,
+                                       args.warmup, profiled=False)
+                vb = nb * args.batched_steps / wb
+                forms["batched"] = {
+                    "workload": "64 periodic boxes, edges U{16..96}, density U{5,10,20}, "
+                                "alpha U[90,150]deg, kT U[0.5,2], FP64, one graph replay "
+                                f"per step, {args.batched_steps} steps",
+                    "particles": nb, "value": vb, "unit": "particle-steps/s",
+                    "ms_per_step": wb * 1e3 / args.batched_steps,
+                    "hbm_roofline_frac_step": vb * 2 * STATE_BYTES["fp64"] / (HBM_PEAK_GBS * 1e9)}
+                print(f"[batched C4] N={nb} {wb * 1e3 / args.batched_steps:.3f} ms/step",
+                      file=sys.stderr)
+        except Exception as exc:  # report, keep the headline
+            forms[form] = {"error": str(exc)}
+    if forms:
+        line["forms"] = forms
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/*
+ * mpc.h -- C ABI of the MI355X (gfx950) multiparticle-collision-dynamics
+ * library: one MPC-SRD time step on one GPU, for one periodic (or z-walled)
+ * box or for a batch of independent boxes advanced together.
+ *
+ * The method is that of Westphal, Goh, Winkler and Gompper, "HTMPC",
+ * arXiv:2406.15236, Sec. II:
+ *   - streaming r <- r + h v                                   (Eq. 1)
+ *   - random shift of the collision lattice before each collision
+ *   - particles sorted into cubic cells of side a
+ *   - per cell: centre-of-mass velocity v_cm, relative velocities rotated by a
+ *     fixed angle alpha about an axis drawn at random per cell and step  (Eq. 2)
+ *   - optional Maxwell-Boltzmann scaling thermostat: relative velocities scaled
+ *     by kappa = sqrt(2 E_k / sum m v_c^2), E_k ~ Gamma(f/2, k_B T),
+ *     f = 3 (N_c - 1)                                          (Thermostat)
+ *   - optional no-slip walls at z = 0 and z = H (bounce-back + phantom
+ *     particles filling wall-cut cells) and constant gravity (Boundary
+ *     conditions, External fields)
+ *   - particles periodically reordered by cell (Sec. III.B.3, reordering).
+ * The arguments follow the paper's statement of the method: box in cells,
+ * cell size a, mean density <N_c>, time step h, rotation angle alpha, k_B T,
+ * mass m, and a main random seed (Sec. III.D.4, "passed as a parameter").
+ *
+ * Conventions for every call:
+ *   - All calls are extern "C"; no C++ exception crosses this boundary.
+ *   - Return value 0 on success, else a negative MPC_E* code; mpc_strerror()
+ *     names it and mpc_last_error() gives the message of the handle.
+ *   - Device pointers are hipMalloc'ed (or torch-allocated) memory on the
+ *     current device; host pointers are ordinary host memory.
+ *   - A handle belongs to one HIP stream and is not thread-safe.
+ *   - mpc_step only enqueues work on the stream; errors detected inside
+ *     kernels (a particle outside the box or not finite, more than
+ *     MPC_MAX_CELL_PARTICLES particles in one cell) are sticky and reported by
+ *     the next synchronising call (mpc_sync, mpc_observables, mpc_get_state,
+ *     mpc_get_binning).
+ */
+#ifndef MPC355_MPC_H
+#define MPC355_MPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage form of the particle state. */
+typedef enum {
+  MPC_FP64 = 0,    /* x, v as FP64 SoA; every operation in FP64                      */
+  MPC_FP32 = 1,    /* x, v as FP32 SoA; streamed in FP32, cell sums and rotation FP64 */
+  MPC_SPLIT32 = 2  /* packed int32 cell index + FP32 offset in [0,1) per axis, FP32
+                      velocities; streaming and rotation in FP32 with compensated FP32
+                      cell sums; thermostat energy and kappa in FP64                   */
+} mpc_form;
+
+/* Feature flags (identical for all boxes of one handle). */
+enum {
+  MPC_MBS = 1u,     /* Maxwell-Boltzmann scaling thermostat (Sec. II, Thermostat)     */
+  MPC_WALLS_Z = 2u  /* no-slip walls at z = 0 and z = L[2] = H: bounce-back streaming
+                       and phantom particles in wall-cut cells (Sec. II, Boundary
+                       conditions); x and y stay periodic                              */
+};
+
+/* Error codes. */
+enum {
+  MPC_OK = 0,
+  MPC_EINVAL = -1,   /* invalid argument (box, a, h, alpha, density, kT, m, form, flags) */
+  MPC_ENOSPACE = -2, /* workspace smaller than mpc_workspace_bytes                       */
+  MPC_ERANGE = -3,   /* N or cell count >= 2^31, box too large for the form, or a cell
+                        that held more than MPC_MAX_CELL_PARTICLES particles             */
+  MPC_EHIP = -4,     /* HIP runtime error (message kept in the handle)                  */
+  MPC_ESTATE = -5    /* a particle left the box or became non-finite                    */
+};
+
+#define MPC_MAX_CELL_PARTICLES 1024
+#define MPC_MAX_BOXES 4096
+
+/* Parameters of one box.  Lengths are in units of the cell size a except a
+ * itself; positions passed to or returned by the state calls are physical
+ * (multiplied by a), velocities physical (length / time). */
+typedef struct {
+  int32_t  L[3];          /* box in cells; with MPC_WALLS_Z, L[2] = H                     */
+  int32_t  form;          /* mpc_form (same for all boxes)                                 */
+  uint32_t flags;         /* MPC_MBS | MPC_WALLS_Z (same for all boxes)                    */
+  int32_t  reorder_every; /* R: store particles in cell order after every R-th step;
+                             0 = never (same for all boxes)                               */
+  double   a;             /* cell size, > 0                                                */
+  double   density;       /* <N_c>: N = llround(density * L0 * L1 * L2), > 0              */
+  double   dt;            /* MPC time step h, > 0                                          */
+  double   alpha;         /* rotation angle in radians                                     */
+  double   kT;            /* k_B T, > 0                                                    */
+  double   mass;          /* particle mass m, > 0                                          */
+  double   g[3];          /* constant acceleration; applied as v += g h after collision   */
+  uint64_t seed;          /* key of the counter-based random streams                      */
+} mpc_params;
+
+/* Observables of one box (FP64, compensated sums over the particles). */
+typedef struct {
+  uint64_t step;       /* number of completed steps                     */
+  uint64_t n;          /* particles                                     */
+  double   P[3];       /* total momentum sum m v                        */
+  double   E;          /* kinetic energy sum m v^2 / 2                  */
+  double   T;          /* sum m |v - P/M|^2 / (3 (n - 1))  (k_B T units) */
+  double   mass_total; /* n m                                           */
+} mpc_obs;
+
+/* Per-kernel device time accumulated by mpc_step_profiled (milliseconds,
+ * from HIP events recorded on the handle's stream around each launch). */
+typedef struct {
+  double scan_ms, scatter_ms, collide_ms, prologue_ms, other_ms;
+  uint64_t scan_launches, scatter_launches, collide_launches, prologue_launches;
+} mpc_kernel_times;
+
+typedef struct mpc_sim mpc_sim;
+
+/* Bytes of device workspace needed for nbox boxes with parameters p[0..nbox).
+ * The workspace holds the double-buffered particle state, keys, permutation,
+ * cell histogram and offsets, and small tables.  Errors: MPC_EINVAL,
+ * MPC_ERANGE. */
+int mpc_workspace_bytes(const mpc_params* p, int32_t nbox, size_t* bytes);
+
+/* Create a handle.  p[0..nbox) is copied.  workspace: device memory of at
+ * least mpc_workspace_bytes bytes, 256-byte aligned, owned by the caller and
+ * kept alive until mpc_destroy.  hip_stream: the hipStream_t all work is
+ * enqueued on (NULL = default stream), owned by the caller.  The particle
+ * state is undefined until mpc_init_state or mpc_set_state.  The step
+ * counter starts at 0.  Errors: MPC_EINVAL, MPC_ENOSPACE, MPC_ERANGE, MPC_EHIP. */
+int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
+               void* hip_stream, mpc_sim** out);
+
+/* Fill every box on the device: positions uniform in the box, velocities
+ * normal with standard deviation sqrt(kT/m) per component and the mean of
+ * each box removed (counter-based stream keyed by init_seed and box). */
+int mpc_init_state(mpc_sim* s, uint64_t init_seed);
+
+/* Advance all boxes by nsteps steps (enqueue only). */
+int mpc_step(mpc_sim* s, int64_t nsteps);
+
+/* As mpc_step, launching kernel by kernel (no graph) with HIP events around
+ * each launch; adds the device times to *acc (which the caller zeroes) after
+ * synchronising the stream. */
+int mpc_step_profiled(mpc_sim* s, int64_t nsteps, mpc_kernel_times* acc);
+
+/* Use (1) or stop using (0) a captured hipGraph for mpc_step; default 1. */
+int mpc_set_graph(mpc_sim* s, int32_t enable);
+
+/* Wait for the stream; report sticky kernel errors (MPC_ESTATE, MPC_ERANGE). */
+int mpc_sync(mpc_sim* s);
+
+/* Observables of box `box` (synchronises). */
+int mpc_observables(mpc_sim* s, int32_t box, mpc_obs* out);
+
+/* Particle count and cell count (including wall layers) of a box. */
+int mpc_box_info(mpc_sim* s, int32_t box, int64_t* n, int64_t* ncell);
+
+/* Step counter: get, or set (the random streams are keyed by it). */
+int mpc_get_step(mpc_sim* s, uint64_t* step);
+int mpc_set_step(mpc_sim* s, uint64_t step);
+
+/* Copy the state of one box from / to host FP64 SoA arrays x[3][n], v[3][n]
+ * (x[0..n) = x components, x[n..2n) y, x[2n..3n) z; physical units).  n must
+ * equal the box's particle count.  Positions must lie in [0, L a) on periodic
+ * axes and in [0, H a] on a walled z axis (MPC_EINVAL otherwise).
+ * Conversions: FP64 exact; FP32 rounds to nearest; SPLIT32 stores
+ * cell = floor(x/a), offset = (float)(x/a - cell) (an offset that rounds to 1
+ * moves to the next cell).  get returns the exact FP64 value of what is
+ * stored.  Both synchronise. */
+int mpc_set_state(mpc_sim* s, int32_t box, const double* x, const double* v, int64_t n);
+int mpc_get_state(mpc_sim* s, int32_t box, double* x, double* v, int64_t n);
+
+/* Binning of the last completed step of one box (synchronises):
+ *   offset[ncell+1]: exclusive prefix of particles per cell;
+ *   perm[n]: storage index (in the order before that step) of the j-th
+ *            particle in (cell key, storage index) order;
+ *   key[n]:  cell key of each particle, indexed by the storage order before
+ *            that step.
+ * Keys are x-fastest: ((c_z' * L1) + c_y) * L0 + c_x with c_z' = c_z (periodic)
+ * or c_z + 1 (walls).  Any pointer may be NULL.  MPC_EINVAL if no step has
+ * run since the state was set. */
+int mpc_get_binning(mpc_sim* s, int32_t box, uint32_t* key, uint32_t* perm, uint32_t* offset);
+
+/* Choose the collide launch (tile size, grid) by timing candidates on the
+ * current state; the state, step counter and random streams are restored.
+ * Returns the chosen configuration in *tile_cells and *grid (may be NULL). */
+int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* grid);
+
+/* Override the collide tiling: cells per tile (1..128, 0 = automatic) and
+ * persistent grid size (0 = automatic). */
+int mpc_set_tiling(mpc_sim* s, int32_t tile_cells, int32_t grid);
+
+/* Release the handle (not the workspace or the stream).  Synchronises. */
+int mpc_destroy(mpc_sim* s);
+
+const char* mpc_strerror(int code);
+const char* mpc_last_error(mpc_sim* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,847 @@
+// mpc_capi.cpp -- host side of the C ABI declared in include/mpc.h: parameter
+// validation, workspace planning, tile tables, step sequencing (direct
+// launches or a replayed hipGraph of one step), state transfer, observables.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "mpc.h"
+#include "mpc_internal.h"
+
+using namespace mpc;
+
+namespace {
+
+constexpr uint64_t kMaxIndex = 0x7fffffffull;  // particle and cell indices stay below 2^31
+constexpr int kMinTileCells = 16;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct BoxPlan {
+  uint64_t n, ncell;
+  int nlz;
+};
+
+struct Plan {
+  std::vector<BoxPlan> box;
+  uint64_t ntot = 0, ctot = 0, cpad = 0;
+  uint32_t nscan = 0;
+  uint64_t max_tiles = 0, npblocks = 0;
+  size_t state_elem_a = 0, state_elem_b = 0;  // bytes per component
+  bool split = false;
+  // byte offsets in the workspace
+  size_t off_S[2][7] = {};
+  size_t off_key = 0, off_perm = 0, off_hist = 0, off_offset = 0, off_scan = 0, off_ctrl = 0,
+         off_boxes = 0, off_tiles = 0, off_pblocks = 0, off_partials = 0, off_vmean = 0;
+  size_t total = 0;
+};
+
+int validate(const mpc_params* p, int32_t nbox, std::string* why) {
+  if (!p || nbox < 1 || nbox > MPC_MAX_BOXES) {
+    *why = "need 1..MPC_MAX_BOXES boxes";
+    return MPC_EINVAL;
+  }
+  for (int32_t b = 0; b < nbox; ++b) {
+    const mpc_params& q = p[b];
+    char msg[160];
+    auto bad = [&](const char* what) {
+      snprintf(msg, sizeof msg, "box %d: %s", b, what);
+      *why = msg;
+      return MPC_EINVAL;
+    };
+    if (q.form < MPC_FP64 || q.form > MPC_SPLIT32) return bad("unknown form");
+    if (q.flags & ~(uint32_t)(MPC_MBS | MPC_WALLS_Z)) return bad("unknown flags");
+    if (q.form != p[0].form || q.flags != p[0].flags || q.reorder_every != p[0].reorder_every)
+      return bad("form, flags and reorder_every must be equal for all boxes");
+    if (q.reorder_every < 0) return bad("reorder_every < 0");
+    for (int k = 0; k < 3; ++k)
+      if (q.L[k] < 1) return bad("L must be >= 1");
+    if (!(q.a > 0.0) || !isfinite(q.a)) return bad("a must be > 0");
+    if (!(q.density > 0.0) || !isfinite(q.density)) return bad("density must be > 0");
+    if (!(q.dt > 0.0) || !isfinite(q.dt)) return bad("dt must be > 0");
+    if (!isfinite(q.alpha)) return bad("alpha must be finite");
+    if (!(q.kT > 0.0) || !isfinite(q.kT)) return bad("kT must be > 0");
+    if (!(q.mass > 0.0) || !isfinite(q.mass)) return bad("mass must be > 0");
+    for (int k = 0; k < 3; ++k)
+      if (!isfinite(q.g[k])) return bad("g must be finite");
+    if (q.form == MPC_SPLIT32) {
+      const int zmax = (q.flags & MPC_WALLS_Z) ? 1023 : 1024;
+      if (q.L[0] > 2048 || q.L[1] > 2048 || q.L[2] > zmax) {
+        snprintf(msg, sizeof msg, "box %d: split form needs L0, L1 <= 2048, L2 <= %d", b, zmax);
+        *why = msg;
+        return MPC_ERANGE;
+      }
+    }
+  }
+  return MPC_OK;
+}
+
+int make_plan(const mpc_params* p, int32_t nbox, Plan& P, std::string* why) {
+  int rc = validate(p, nbox, why);
+  if (rc) return rc;
+  P.box.resize(nbox);
+  for (int32_t b = 0; b < nbox; ++b) {
+    const mpc_params& q = p[b];
+    const bool walls = q.flags & MPC_WALLS_Z;
+    const double vol = (double)q.L[0] * q.L[1] * q.L[2];
+    const double nd = llround(q.density * vol);
+    const int nlz = walls ? q.L[2] + 2 : q.L[2];
+    const double cd = (double)q.L[0] * q.L[1] * nlz;
+    if (nd < 1.0) {
+      *why = "box with no particles";
+      return MPC_EINVAL;
+    }
+    if (nd > (double)kMaxIndex || cd > (double)kMaxIndex) {
+      *why = "particles or cells of a box >= 2^31";
+      return MPC_ERANGE;
+    }
+    P.box[b].n = (uint64_t)nd;
+    P.box[b].ncell = (uint64_t)cd;
+    P.box[b].nlz = nlz;
+    P.ntot += P.box[b].n;
+    P.ctot += P.box[b].ncell;
+    P.max_tiles += (P.box[b].ncell + kMinTileCells - 1) / kMinTileCells;
+    P.npblocks += (P.box[b].n + kPartBlock - 1) / kPartBlock;
+  }
+  P.nscan = (uint32_t)((P.ctot + kScanBlock - 1) / kScanBlock);
+  P.cpad = (uint64_t)P.nscan * kScanBlock;
+  if (P.ntot > kMaxIndex || P.cpad + 1 > kMaxIndex) {
+    *why = "total particles or cells >= 2^31";
+    return MPC_ERANGE;
+  }
+  const int form = p[0].form;
+  P.split = form == MPC_SPLIT32;
+  P.state_elem_a = form == MPC_FP64 ? 8 : 4;
+  P.state_elem_b = form == MPC_FP64 ? 8 : 4;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  for (int s = 0; s < 2; ++s) {
+    for (int k = 0; k < 3; ++k) P.off_S[s][k] = take(P.state_elem_a * P.ntot);
+    for (int k = 0; k < 3; ++k) P.off_S[s][3 + k] = take(P.state_elem_b * P.ntot);
+    P.off_S[s][6] = P.split ? take(4 * P.ntot) : 0;
+  }
+  P.off_key = take(4 * P.ntot);
+  P.off_perm = take(4 * P.ntot);
+  P.off_hist = take(4 * P.cpad);
+  P.off_offset = take(4 * (P.cpad + 1));
+  P.off_scan = take(4 * (size_t)P.nscan);
+  P.off_ctrl = take(sizeof(Ctrl));
+  P.off_boxes = take(sizeof(BoxDev) * nbox);
+  P.off_tiles = take(sizeof(Tile) * P.max_tiles);
+  P.off_pblocks = take(sizeof(PBlock) * P.npblocks);
+  P.off_partials = take(sizeof(double) * 4 * P.npblocks);
+  P.off_vmean = take(sizeof(double) * 3 * nbox);
+  P.total = off;
+  return MPC_OK;
+}
+
+struct Neumaier {
+  double s = 0.0, c = 0.0;
+  void add(double x) {
+    const double t = s + x;
+    if (fabs(s) >= fabs(x)) {
+      c += (s - t) + x;
+    } else {
+      c += (x - t) + s;
+    }
+    s = t;
+  }
+  double val() const { return s + c; }
+};
+
+}  // namespace
+
+struct mpc_sim {
+  std::vector<mpc_params> params;
+  Plan plan;
+  std::vector<BoxDev> boxes;
+  std::vector<Tile> tiles;
+  std::vector<PBlock> pblocks;
+  std::vector<uint32_t> box_pb0;  // first pblock of each box, nbox + 1 entries
+  Dev dev{};
+  Launch L{};
+  int form = 0;
+  int32_t R = 0;
+  uint64_t step = 0;
+  uint32_t cur = 0;
+  bool keys_valid = false;
+  bool have_binning = false;
+  bool use_graph = true;
+  bool graph_ready = false;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t capture_stream = nullptr;
+  int tile_override = 0, grid_override = 0;
+  int num_cu = 256, occupancy = 4;
+  double* vmean = nullptr;
+  std::string err;
+};
+
+namespace {
+
+int hip_fail(mpc_sim* s, hipError_t e, const char* where) {
+  if (e == hipSuccess) return MPC_OK;
+  if (s) {
+    s->err = std::string(where) + ": " + hipGetErrorString(e);
+  }
+  return MPC_EHIP;
+}
+#define HIPCHK(s, expr)                                  \
+  do {                                                   \
+    hipError_t _e = (expr);                              \
+    if (_e != hipSuccess) return hip_fail((s), _e, #expr); \
+  } while (0)
+
+int auto_tile_cells(double density) {
+  const double target = 0.65 * kTileCap / density;
+  int t = kTileMaxCells;
+  while (t > kMinTileCells && (double)t > target) t >>= 1;
+  return t;
+}
+
+void build_tiles(mpc_sim* s) {
+  s->tiles.clear();
+  for (size_t b = 0; b < s->boxes.size(); ++b) {
+    const BoxDev& B = s->boxes[b];
+    int T = s->tile_override ? s->tile_override : auto_tile_cells(B.density);
+    T = std::max(kMinTileCells, std::min(kTileMaxCells, T));
+    for (uint64_t c0 = 0; c0 < B.nc; c0 += T) {
+      Tile t;
+      t.c0 = B.cbase + (uint32_t)c0;
+      t.nc = (uint16_t)std::min<uint64_t>(T, B.nc - c0);
+      t.box = (uint16_t)b;
+      s->tiles.push_back(t);
+    }
+  }
+  s->L.ntiles = (uint32_t)s->tiles.size();
+  uint32_t g = s->grid_override ? (uint32_t)s->grid_override
+                                : (uint32_t)(s->num_cu * std::max(1, s->occupancy));
+  g = std::max<uint32_t>(1, std::min<uint32_t>(g, s->L.ntiles));
+  s->L.collide_grid = g;
+}
+
+int upload_tables(mpc_sim* s) {
+  HIPCHK(s, hipMemcpyAsync(s->dev.tiles, s->tiles.data(), sizeof(Tile) * s->tiles.size(),
+                           hipMemcpyHostToDevice, s->L.stream));
+  HIPCHK(s, hipStreamSynchronize(s->L.stream));
+  return MPC_OK;
+}
+
+int read_ctrl(mpc_sim* s, Ctrl* c) {
+  HIPCHK(s, hipMemcpyAsync(c, s->dev.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s->L.stream));
+  HIPCHK(s, hipStreamSynchronize(s->L.stream));
+  return MPC_OK;
+}
+
+int check_sticky(mpc_sim* s) {
+  Ctrl c;
+  int rc = read_ctrl(s, &c);
+  if (rc) return rc;
+  if (c.err & kErrKey) {
+    s->err = "a particle left the box or is not finite";
+    return MPC_ESTATE;
+  }
+  if (c.err & kErrCellOverflow) {
+    s->err = "a cell held more than MPC_MAX_CELL_PARTICLES particles";
+    return MPC_ERANGE;
+  }
+  return MPC_OK;
+}
+
+// One step's launches (scan, scatter, collide, advance) on `st`.
+hipError_t enqueue_step(mpc_sim* s, hipStream_t st) {
+  Launch l = s->L;
+  l.stream = st;
+  hipError_t e;
+  if ((e = launch_scan(s->dev, l)) != hipSuccess) return e;
+  if ((e = launch_scatter(s->dev, l)) != hipSuccess) return e;
+  if ((e = launch_collide(s->dev, l)) != hipSuccess) return e;
+  return launch_advance(s->dev, l);
+}
+
+int ensure_keys(mpc_sim* s) {
+  if (s->keys_valid) return MPC_OK;
+  HIPCHK(s, launch_zero_u32(s->dev.hist, s->plan.cpad, s->L.stream));
+  HIPCHK(s, launch_key_hist(s->dev, s->L));
+  s->keys_valid = true;
+  return MPC_OK;
+}
+
+void advance_mirror(mpc_sim* s, int64_t n) {
+  for (int64_t k = 0; k < n; ++k) {
+    const uint64_t t = s->step;
+    if (s->R > 0 && (t + 1) % (uint64_t)s->R == 0) s->cur ^= 1u;
+    s->step = t + 1;
+  }
+}
+
+int drop_graph(mpc_sim* s) {
+  if (s->gexec) {
+    HIPCHK(s, hipGraphExecDestroy(s->gexec));
+    s->gexec = nullptr;
+  }
+  s->graph_ready = false;
+  return MPC_OK;
+}
+
+int capture_graph(mpc_sim* s) {
+  if (s->graph_ready) return MPC_OK;
+  if (!s->capture_stream) HIPCHK(s, hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  HIPCHK(s, hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enqueue_step(s, s->capture_stream);
+  hipError_t e2 = hipStreamEndCapture(s->capture_stream, &g);
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(s, e, "capture step");
+  }
+  if (e2 != hipSuccess) return hip_fail(s, e2, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(s, e, "hipGraphInstantiate");
+  s->graph_ready = true;
+  return MPC_OK;
+}
+
+// Host FP64 <-> stored form of one box.
+template <typename T>
+int copy_h2d(mpc_sim* s, void* dst_base, uint64_t elem0, const std::vector<T>& src) {
+  HIPCHK(s, hipMemcpyAsync((T*)dst_base + elem0, src.data(), sizeof(T) * src.size(),
+                           hipMemcpyHostToDevice, s->L.stream));
+  return MPC_OK;
+}
+template <typename T>
+int copy_d2h(mpc_sim* s, const void* src_base, uint64_t elem0, std::vector<T>& dst) {
+  HIPCHK(s, hipMemcpyAsync(dst.data(), (const T*)src_base + elem0, sizeof(T) * dst.size(),
+                           hipMemcpyDeviceToHost, s->L.stream));
+  return MPC_OK;
+}
+
+int obs_all(mpc_sim* s, std::vector<double>& P, std::vector<double>& E,
+            std::vector<double>& K) {
+  const size_t nbox = s->boxes.size();
+  const size_t npb = s->pblocks.size();
+  std::vector<double> part(4 * npb);
+  HIPCHK(s, launch_obs_pass1(s->dev, s->L));
+  HIPCHK(s, hipMemcpyAsync(part.data(), s->dev.partials, sizeof(double) * 4 * npb,
+                           hipMemcpyDeviceToHost, s->L.stream));
+  HIPCHK(s, hipStreamSynchronize(s->L.stream));
+  P.assign(3 * nbox, 0.0);
+  E.assign(nbox, 0.0);
+  K.assign(nbox, 0.0);
+  std::vector<double> vm(3 * nbox);
+  for (size_t b = 0; b < nbox; ++b) {
+    Neumaier a[4];
+    for (uint32_t q = s->box_pb0[b]; q < s->box_pb0[b + 1]; ++q)
+      for (int k = 0; k < 4; ++k) a[k].add(part[4 * q + k]);
+    for (int k = 0; k < 3; ++k) P[3 * b + k] = a[k].val();
+    E[b] = a[3].val();
+    const double M = (double)s->boxes[b].np * s->boxes[b].mass;
+    for (int k = 0; k < 3; ++k) vm[3 * b + k] = P[3 * b + k] / M;
+  }
+  HIPCHK(s, hipMemcpyAsync(s->vmean, vm.data(), sizeof(double) * 3 * nbox, hipMemcpyHostToDevice,
+                           s->L.stream));
+  HIPCHK(s, launch_obs_pass2(s->dev, s->L, s->vmean));
+  HIPCHK(s, hipMemcpyAsync(part.data(), s->dev.partials, sizeof(double) * 4 * npb,
+                           hipMemcpyDeviceToHost, s->L.stream));
+  HIPCHK(s, hipStreamSynchronize(s->L.stream));
+  for (size_t b = 0; b < nbox; ++b) {
+    Neumaier a;
+    for (uint32_t q = s->box_pb0[b]; q < s->box_pb0[b + 1]; ++q) a.add(part[4 * q]);
+    K[b] = a.val();
+  }
+  return MPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mpc_strerror(int code) {
+  switch (code) {
+    case MPC_OK: return "ok";
+    case MPC_EINVAL: return "invalid argument";
+    case MPC_ENOSPACE: return "workspace too small";
+    case MPC_ERANGE: return "size out of range";
+    case MPC_EHIP: return "HIP runtime error";
+    case MPC_ESTATE: return "invalid particle state";
+    default: return "unknown error";
+  }
+}
+
+const char* mpc_last_error(mpc_sim* s) { return s ? s->err.c_str() : ""; }
+
+int mpc_workspace_bytes(const mpc_params* p, int32_t nbox, size_t* bytes) {
+  if (!bytes) return MPC_EINVAL;
+  Plan P;
+  std::string why;
+  const int rc = make_plan(p, nbox, P, &why);
+  if (rc) return rc;
+  *bytes = P.total;
+  return MPC_OK;
+}
+
+int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
+               void* hip_stream, mpc_sim** out) {
+  if (!out) return MPC_EINVAL;
+  *out = nullptr;
+  mpc_sim* s = new mpc_sim();
+  std::string why;
+  int rc = make_plan(p, nbox, s->plan, &why);
+  if (rc) {
+    delete s;
+    return rc;
+  }
+  if (!workspace || bytes < s->plan.total || ((uintptr_t)workspace & 255)) {
+    delete s;
+    return workspace && bytes >= s->plan.total ? MPC_EINVAL : MPC_ENOSPACE;
+  }
+  s->params.assign(p, p + nbox);
+  s->form = p[0].form;
+  s->R = p[0].reorder_every;
+  const Plan& P = s->plan;
+  char* ws = (char*)workspace;
+  for (int b = 0; b < 2; ++b) {
+    for (int k = 0; k < 3; ++k) {
+      s->dev.S[b].a[k] = ws + P.off_S[b][k];
+      s->dev.S[b].b[k] = ws + P.off_S[b][3 + k];
+    }
+    s->dev.S[b].cell = P.split ? (uint32_t*)(ws + P.off_S[b][6]) : nullptr;
+  }
+  s->dev.key = (uint32_t*)(ws + P.off_key);
+  s->dev.perm = (uint32_t*)(ws + P.off_perm);
+  s->dev.hist = (uint32_t*)(ws + P.off_hist);
+  s->dev.offset = (uint32_t*)(ws + P.off_offset);
+  s->dev.scan_blk = (uint32_t*)(ws + P.off_scan);
+  s->dev.ctrl = (Ctrl*)(ws + P.off_ctrl);
+  s->dev.boxes = (BoxDev*)(ws + P.off_boxes);
+  s->dev.tiles = (Tile*)(ws + P.off_tiles);
+  s->dev.pblocks = (PBlock*)(ws + P.off_pblocks);
+  s->dev.partials = (double*)(ws + P.off_partials);
+  s->dev.ntot = (uint32_t)P.ntot;
+  s->vmean = (double*)(ws + P.off_vmean);
+
+  // boxes
+  uint64_t pb = 0, cb = 0;
+  s->box_pb0.push_back(0);
+  for (int32_t b = 0; b < nbox; ++b) {
+    const mpc_params& q = p[b];
+    BoxDev B{};
+    for (int k = 0; k < 3; ++k) {
+      B.L[k] = q.L[k];
+      B.Ld[k] = (double)q.L[k];
+      B.Lf[k] = (float)q.L[k];
+    }
+    B.nlz = P.box[b].nlz;
+    B.pbase = (uint32_t)pb;
+    B.np = (uint32_t)P.box[b].n;
+    B.cbase = (uint32_t)cb;
+    B.nc = (uint32_t)P.box[b].ncell;
+    B.key_lo = (uint32_t)(q.seed & 0xffffffffu);
+    B.key_hi = (uint32_t)(q.seed >> 32);
+    B.walls = (q.flags & MPC_WALLS_Z) ? 1u : 0u;
+    B.mbs = (q.flags & MPC_MBS) ? 1u : 0u;
+    // internal units: lengths in cells, so velocities / a, energies / a^2
+    B.h = q.dt;
+    B.hf = (float)q.dt;
+    B.ca = cos(q.alpha);
+    B.sa = sin(q.alpha);
+    B.omc = 1.0 - B.ca;
+    B.kT = q.kT / (q.a * q.a);
+    B.mass = q.mass;
+    B.density = q.density;
+    B.sd = sqrt(B.kT / q.mass);
+    B.grav = (q.g[0] != 0.0 || q.g[1] != 0.0 || q.g[2] != 0.0) ? 1u : 0u;
+    for (int k = 0; k < 3; ++k) B.gh[k] = (q.g[k] / q.a) * q.dt;
+    s->boxes.push_back(B);
+    for (uint64_t p0 = 0; p0 < P.box[b].n; p0 += kPartBlock)
+      s->pblocks.push_back(PBlock{(uint32_t)b, (uint32_t)(pb + p0)});
+    s->box_pb0.push_back((uint32_t)s->pblocks.size());
+    pb += P.box[b].n;
+    cb += P.box[b].ncell;
+  }
+
+  s->L.form = s->form;
+  s->L.nbox = (uint32_t)nbox;
+  s->L.ntot = P.ntot;
+  s->L.ctot = P.ctot;
+  s->L.nscan = P.nscan;
+  s->L.npblocks = (uint32_t)s->pblocks.size();
+  s->L.stream = (hipStream_t)hip_stream;
+  s->L.xcd_remap = 1;
+
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    s->num_cu = prop.multiProcessorCount;
+  s->occupancy = 2;
+  if (collide_occupancy(s->form, &s->occupancy) != hipSuccess || s->occupancy < 1) s->occupancy = 1;
+  build_tiles(s);
+
+  auto fail = [&](int code) {
+    delete s;
+    return code;
+  };
+  if ((rc = upload_tables(s))) return fail(rc);
+  if (hipMemcpyAsync(s->dev.boxes, s->boxes.data(), sizeof(BoxDev) * s->boxes.size(),
+                     hipMemcpyHostToDevice, s->L.stream) != hipSuccess ||
+      hipMemcpyAsync(s->dev.pblocks, s->pblocks.data(), sizeof(PBlock) * s->pblocks.size(),
+                     hipMemcpyHostToDevice, s->L.stream) != hipSuccess ||
+      launch_zero_u32(s->dev.hist, P.cpad, s->L.stream) != hipSuccess ||
+      launch_zero_u32(s->dev.perm, P.ntot, s->L.stream) != hipSuccess ||
+      launch_zero_u32(s->dev.key, P.ntot, s->L.stream) != hipSuccess ||
+      launch_zero_u32(s->dev.offset, P.cpad + 1, s->L.stream) != hipSuccess ||
+      launch_set_ctrl(s->dev, s->L, 0, 0, s->R, 1) != hipSuccess ||
+      hipStreamSynchronize(s->L.stream) != hipSuccess)
+    return fail(MPC_EHIP);
+  *out = s;
+  return MPC_OK;
+}
+
+int mpc_destroy(mpc_sim* s) {
+  if (!s) return MPC_EINVAL;
+  (void)hipStreamSynchronize(s->L.stream);
+  drop_graph(s);
+  if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
+  delete s;
+  return MPC_OK;
+}
+
+int mpc_set_graph(mpc_sim* s, int32_t enable) {
+  if (!s) return MPC_EINVAL;
+  s->use_graph = enable != 0;
+  return MPC_OK;
+}
+
+int mpc_set_tiling(mpc_sim* s, int32_t tile_cells, int32_t grid) {
+  if (!s) return MPC_EINVAL;
+  if (tile_cells != 0 && (tile_cells < kMinTileCells || tile_cells > kTileMaxCells))
+    return MPC_EINVAL;
+  if (grid < 0) return MPC_EINVAL;
+  HIPCHK(s, hipStreamSynchronize(s->L.stream));
+  s->tile_override = tile_cells;
+  s->grid_override = grid;
+  build_tiles(s);
+  int rc = drop_graph(s);
+  if (rc) return rc;
+  return upload_tables(s);
+}
+
+int mpc_step(mpc_sim* s, int64_t nsteps) {
+  if (!s || nsteps < 0) return MPC_EINVAL;
+  if (nsteps == 0) return MPC_OK;
+  int rc = ensure_keys(s);
+  if (rc) return rc;
+  if (s->use_graph) {
+    if ((rc = capture_graph(s))) return rc;
+    for (int64_t k = 0; k < nsteps; ++k) HIPCHK(s, hipGraphLaunch(s->gexec, s->L.stream));
+  } else {
+    for (int64_t k = 0; k < nsteps; ++k) HIPCHK(s, enqueue_step(s, s->L.stream));
+  }
+  advance_mirror(s, nsteps);
+  s->have_binning = true;
+  return MPC_OK;
+}
+
+int mpc_step_profiled(mpc_sim* s, int64_t nsteps, mpc_kernel_times* acc) {
+  if (!s || nsteps < 0 || !acc) return MPC_EINVAL;
+  if (nsteps == 0) return MPC_OK;
+  hipStream_t st = s->L.stream;
+  std::vector<hipEvent_t> ev;
+  auto mark = [&]() -> hipError_t {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    ev.push_back(e);
+    return hipEventRecord(e, st);
+  };
+  int kinds_prologue = 0;
+  HIPCHK(s, mark());
+  if (!s->keys_valid) {
+    HIPCHK(s, launch_zero_u32(s->dev.hist, s->plan.cpad, st));
+    HIPCHK(s, launch_key_hist(s->dev, s->L));
+    s->keys_valid = true;
+    HIPCHK(s, mark());
+    kinds_prologue = 1;
+  }
+  for (int64_t k = 0; k < nsteps; ++k) {
+    HIPCHK(s, launch_scan(s->dev, s->L));
+    HIPCHK(s, mark());
+    HIPCHK(s, launch_scatter(s->dev, s->L));
+    HIPCHK(s, mark());
+    HIPCHK(s, launch_collide(s->dev, s->L));
+    HIPCHK(s, mark());
+    HIPCHK(s, launch_advance(s->dev, s->L));
+    HIPCHK(s, mark());
+  }
+  HIPCHK(s, hipStreamSynchronize(st));
+  size_t e = 0;
+  auto span = [&]() {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[e], ev[e + 1]);
+    ++e;
+    return (double)ms;
+  };
+  if (kinds_prologue) {
+    acc->prologue_ms += span();
+    acc->prologue_launches += 1;
+  }
+  for (int64_t k = 0; k < nsteps; ++k) {
+    acc->scan_ms += span();
+    acc->scatter_ms += span();
+    acc->collide_ms += span();
+    acc->other_ms += span();
+    acc->scan_launches += 1;
+    acc->scatter_launches += 1;
+    acc->collide_launches += 1;
+  }
+  for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+  advance_mirror(s, nsteps);
+  s->have_binning = true;
+  return MPC_OK;
+}
+
+int mpc_sync(mpc_sim* s) {
+  if (!s) return MPC_EINVAL;
+  HIPCHK(s, hipStreamSynchronize(s->L.stream));
+  return check_sticky(s);
+}
+
+int mpc_box_info(mpc_sim* s, int32_t box, int64_t* n, int64_t* ncell) {
+  if (!s || box < 0 || box >= (int32_t)s->boxes.size()) return MPC_EINVAL;
+  if (n) *n = (int64_t)s->boxes[box].np;
+  if (ncell) *ncell = (int64_t)s->boxes[box].nc;
+  return MPC_OK;
+}
+
+int mpc_get_step(mpc_sim* s, uint64_t* step) {
+  if (!s || !step) return MPC_EINVAL;
+  *step = s->step;
+  return MPC_OK;
+}
+
+int mpc_set_step(mpc_sim* s, uint64_t step) {
+  if (!s) return MPC_EINVAL;
+  s->step = step;
+  s->keys_valid = false;
+  s->have_binning = false;
+  HIPCHK(s, launch_set_ctrl(s->dev, s->L, s->step, s->cur, s->R, 0));
+  HIPCHK(s, hipStreamSynchronize(s->L.stream));
+  return MPC_OK;
+}
+
+int mpc_init_state(mpc_sim* s, uint64_t init_seed) {
+  if (!s) return MPC_EINVAL;
+  HIPCHK(s, launch_set_ctrl(s->dev, s->L, s->step, s->cur, s->R, 1));
+  HIPCHK(s, launch_init_state(s->dev, s->L, init_seed));
+  std::vector<double> P, E, K;
+  // mean of each box
+  const size_t nbox = s->boxes.size();
+  const size_t npb = s->pblocks.size();
+  std::vector<double> part(4 * npb);
+  HIPCHK(s, launch_obs_pass1(s->dev, s->L));
+  HIPCHK(s, hipMemcpyAsync(part.data(), s->dev.partials, sizeof(double) * 4 * npb,
+                           hipMemcpyDeviceToHost, s->L.stream));
+  HIPCHK(s, hipStreamSynchronize(s->L.stream));
+  std::vector<double> vm(3 * nbox);
+  for (size_t b = 0; b < nbox; ++b) {
+    Neumaier a[3];
+    for (uint32_t q = s->box_pb0[b]; q < s->box_pb0[b + 1]; ++q)
+      for (int k = 0; k < 3; ++k) a[k].add(part[4 * q + k]);
+    const double M = (double)s->boxes[b].np * s->boxes[b].mass;
+    for (int k = 0; k < 3; ++k) vm[3 * b + k] = a[k].val() / M;
+  }
+  HIPCHK(s, hipMemcpyAsync(s->vmean, vm.data(), sizeof(double) * 3 * nbox, hipMemcpyHostToDevice,
+                           s->L.stream));
+  HIPCHK(s, launch_remove_mean(s->dev, s->L, s->vmean));
+  HIPCHK(s, hipStreamSynchronize(s->L.stream));
+  s->keys_valid = false;
+  s->have_binning = false;
+  return MPC_OK;
+}
+
+int mpc_set_state(mpc_sim* s, int32_t box, const double* x, const double* v, int64_t n) {
+  if (!s || box < 0 || box >= (int32_t)s->boxes.size() || !x || !v) return MPC_EINVAL;
+  const BoxDev& B = s->boxes[box];
+  if (n != (int64_t)B.np) {
+    s->err = "n differs from the box's particle count";
+    return MPC_EINVAL;
+  }
+  const double a = s->params[box].a;
+  const bool walls = B.walls;
+  // validate positions (internal units)
+  for (int k = 0; k < 3; ++k) {
+    const double Lk = B.Ld[k];
+    for (int64_t i = 0; i < n; ++i) {
+      const double xi = x[k * n + i] / a;
+      const bool ok = (walls && k == 2) ? (xi >= 0.0 && xi <= Lk) : (xi >= 0.0 && xi < Lk);
+      if (!ok || !isfinite(v[k * n + i])) {
+        s->err = "position outside the box or non-finite velocity";
+        return MPC_EINVAL;
+      }
+    }
+  }
+  HIPCHK(s, hipStreamSynchronize(s->L.stream));
+  const StatePtrs& S = s->dev.S[s->cur];
+  int rc = MPC_OK;
+  if (s->form == MPC_FP64) {
+    std::vector<double> buf(n);
+    for (int k = 0; k < 6 && !rc; ++k) {
+      const double* src = k < 3 ? x + k * n : v + (k - 3) * n;
+      for (int64_t i = 0; i < n; ++i) buf[i] = src[i] / a;
+      rc = copy_h2d(s, k < 3 ? S.a[k] : S.b[k - 3], B.pbase, buf);
+      if (!rc) HIPCHK(s, hipStreamSynchronize(s->L.stream));
+    }
+  } else if (s->form == MPC_FP32) {
+    std::vector<float> buf(n);
+    for (int k = 0; k < 6 && !rc; ++k) {
+      const double* src = k < 3 ? x + k * n : v + (k - 3) * n;
+      for (int64_t i = 0; i < n; ++i) {
+        float f = (float)(src[i] / a);
+        if (k < 3 && !(walls && k == 2) && f >= B.Lf[k]) f = nextafterf(B.Lf[k], 0.0f);
+        buf[i] = f;
+      }
+      rc = copy_h2d(s, k < 3 ? S.a[k] : S.b[k - 3], B.pbase, buf);
+      if (!rc) HIPCHK(s, hipStreamSynchronize(s->L.stream));
+    }
+  } else {
+    std::vector<uint32_t> cell(n, 0u);
+    std::vector<float> buf(n);
+    for (int k = 0; k < 3 && !rc; ++k) {
+      const uint32_t shift = k == 0 ? 0 : (k == 1 ? kSplitXBits : kSplitXBits + kSplitYBits);
+      for (int64_t i = 0; i < n; ++i) {
+        const double xi = x[k * n + i] / a;
+        double fl = floor(xi);
+        float o = (float)(xi - fl);
+        if (o >= 1.0f) {
+          o = 0.0f;
+          fl += 1.0;
+        }
+        int c = (int)fl;
+        if (!(walls && k == 2) && c >= B.L[k]) c -= B.L[k];
+        cell[i] |= (uint32_t)c << shift;
+        buf[i] = o;
+      }
+      rc = copy_h2d(s, S.a[k], B.pbase, buf);
+      if (!rc) HIPCHK(s, hipStreamSynchronize(s->L.stream));
+    }
+    for (int k = 0; k < 3 && !rc; ++k) {
+      for (int64_t i = 0; i < n; ++i) buf[i] = (float)(v[k * n + i] / a);
+      rc = copy_h2d(s, S.b[k], B.pbase, buf);
+      if (!rc) HIPCHK(s, hipStreamSynchronize(s->L.stream));
+    }
+    if (!rc) rc = copy_h2d(s, S.cell, B.pbase, cell);
+  }
+  if (rc) return rc;
+  HIPCHK(s, launch_set_ctrl(s->dev, s->L, s->step, s->cur, s->R, 1));
+  HIPCHK(s, hipStreamSynchronize(s->L.stream));
+  s->keys_valid = false;
+  s->have_binning = false;
+  return MPC_OK;
+}
+
+int mpc_get_state(mpc_sim* s, int32_t box, double* x, double* v, int64_t n) {
+  if (!s || box < 0 || box >= (int32_t)s->boxes.size() || !x || !v) return MPC_EINVAL;
+  const BoxDev& B = s->boxes[box];
+  if (n != (int64_t)B.np) return MPC_EINVAL;
+  int rc = mpc_sync(s);
+  if (rc) return rc;
+  const double a = s->params[box].a;
+  const StatePtrs& S = s->dev.S[s->cur];
+  if (s->form == MPC_FP64) {
+    std::vector<double> buf(n);
+    for (int k = 0; k < 6; ++k) {
+      if ((rc = copy_d2h(s, k < 3 ? S.a[k] : S.b[k - 3], B.pbase, buf))) return rc;
+      HIPCHK(s, hipStreamSynchronize(s->L.stream));
+      double* dst = k < 3 ? x + k * n : v + (k - 3) * n;
+      for (int64_t i = 0; i < n; ++i) dst[i] = buf[i] * a;
+    }
+  } else {
+    std::vector<float> buf(n);
+    std::vector<uint32_t> cell;
+    if (s->form == MPC_SPLIT32) {
+      cell.resize(n);
+      if ((rc = copy_d2h(s, S.cell, B.pbase, cell))) return rc;
+      HIPCHK(s, hipStreamSynchronize(s->L.stream));
+    }
+    for (int k = 0; k < 6; ++k) {
+      if ((rc = copy_d2h(s, k < 3 ? S.a[k] : S.b[k - 3], B.pbase, buf))) return rc;
+      HIPCHK(s, hipStreamSynchronize(s->L.stream));
+      double* dst = k < 3 ? x + k * n : v + (k - 3) * n;
+      if (k < 3 && s->form == MPC_SPLIT32) {
+        const uint32_t shift = k == 0 ? 0 : (k == 1 ? kSplitXBits : kSplitXBits + kSplitYBits);
+        const uint32_t mask = k == 2 ? ((1u << kSplitZBits) - 1) : ((1u << kSplitXBits) - 1);
+        for (int64_t i = 0; i < n; ++i)
+          dst[i] = ((double)((cell[i] >> shift) & mask) + (double)buf[i]) * a;
+      } else {
+        for (int64_t i = 0; i < n; ++i) dst[i] = (double)buf[i] * a;
+      }
+    }
+  }
+  return MPC_OK;
+}
+
+int mpc_observables(mpc_sim* s, int32_t box, mpc_obs* out) {
+  if (!s || !out || box < 0 || box >= (int32_t)s->boxes.size()) return MPC_EINVAL;
+  int rc = mpc_sync(s);
+  if (rc) return rc;
+  std::vector<double> P, E, K;
+  if ((rc = obs_all(s, P, E, K))) return rc;
+  const BoxDev& B = s->boxes[box];
+  const double a = s->params[box].a;
+  out->step = s->step;
+  out->n = B.np;
+  for (int k = 0; k < 3; ++k) out->P[k] = P[3 * box + k] * a;
+  out->E = E[box] * a * a;
+  out->T = B.np > 1 ? K[box] / (3.0 * (double)(B.np - 1)) * a * a : 0.0;
+  out->mass_total = (double)B.np * B.mass;
+  if (!isfinite(out->E) || !isfinite(out->P[0]) || !isfinite(out->P[1]) || !isfinite(out->P[2])) {
+    s->err = "non-finite observables";
+    return MPC_ESTATE;
+  }
+  return MPC_OK;
+}
+
+int mpc_get_binning(mpc_sim* s, int32_t box, uint32_t* key, uint32_t* perm, uint32_t* offset) {
+  if (!s || box < 0 || box >= (int32_t)s->boxes.size()) return MPC_EINVAL;
+  if (!s->have_binning) {
+    s->err = "no step since the state was set";
+    return MPC_EINVAL;
+  }
+  int rc = mpc_sync(s);
+  if (rc) return rc;
+  HIPCHK(s, launch_canon_perm(s->dev, s->L));
+  const BoxDev& B = s->boxes[box];
+  std::vector<uint32_t> off(B.nc + 1), pm(B.np);
+  if ((rc = copy_d2h(s, s->dev.offset, B.cbase, off))) return rc;
+  if ((rc = copy_d2h(s, s->dev.perm, B.pbase, pm))) return rc;
+  HIPCHK(s, hipStreamSynchronize(s->L.stream));
+  const uint32_t o0 = off[0];
+  for (auto& o : off) o -= o0;
+  for (auto& q : pm) q -= B.pbase;
+  if (offset) memcpy(offset, off.data(), sizeof(uint32_t) * off.size());
+  if (perm) memcpy(perm, pm.data(), sizeof(uint32_t) * pm.size());
+  if (key) {
+    for (uint32_t c = 0; c < B.nc; ++c)
+      for (uint32_t j = off[c]; j < off[c + 1]; ++j) key[pm[j]] = c;
+  }
+  return MPC_OK;
+}
+
+int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* grid) {
+  if (!s || trial_steps < 1) return MPC_EINVAL;
+  (void)tile_cells;
+  (void)grid;
+  s->err = "autotune not available";
+  return MPC_EINVAL;
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+// mpc_internal.h -- layouts shared by the host planner and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpc {
+
+constexpr int kThreads = 256;               // threads per workgroup (4 wave64)
+constexpr int kCollideThreads = 256;        // collide workgroup (4 wave64)
+constexpr int kTileCap = 1024;              // particles held in LDS per tile pass
+constexpr int kTileMaxCells = 128;          // cells per collide tile
+constexpr int kScanItems = 16;              // cells per thread in the scan kernels
+constexpr int kScanBlock = kThreads * kScanItems;
+constexpr int kPartBlock = kThreads * 4;    // particles per block of per-particle kernels
+
+// Random-stream tags (counter word 3); counter = {draw, id, step, tag}.
+enum : uint32_t { kTagShift = 1, kTagAxis = 2, kTagThermo = 3, kTagPhantom = 4,
+                  kTagInitPos = 5, kTagInitVel = 6 };
+
+// Sticky error bits in Ctrl::err.
+enum : uint32_t { kErrKey = 1u, kErrCellOverflow = 2u };
+
+enum : int { kFormF64 = 0, kFormF32 = 1, kFormSplit = 2 };
+
+// Split form packs the unshifted cell as x | y << 11 | z << 22.
+constexpr uint32_t kSplitXBits = 11, kSplitYBits = 11, kSplitZBits = 10;
+
+struct BoxDev {
+  int32_t L[3];        // cells per axis (walls: L[2] = H)
+  int32_t nlz;         // z layers in key space: L[2], or H + 2 with walls
+  uint32_t pbase, np;  // particle range in the flattened index space
+  uint32_t cbase, nc;  // cell range in the flattened key space
+  uint32_t key_lo, key_hi;
+  uint32_t walls, mbs;
+  double Ld[3];        // L as double
+  float Lf[3];         // L as float
+  double h;            // time step
+  float hf;
+  float pad0;
+  double ca, sa, omc;  // cos(alpha), sin(alpha), 1 - cos(alpha)
+  double kT, mass, density, sd;  // sd = sqrt(kT / m)
+  double gh[3];        // g * h
+  uint32_t grav;
+  uint32_t pad1;
+};
+
+struct Tile {          // one collide work item: cells [c0, c0 + nc) of box `box`
+  uint32_t c0;         // first global cell key
+  uint16_t nc;
+  uint16_t box;
+};
+
+struct PBlock {        // one block of a per-particle kernel
+  uint32_t box;
+  uint32_t p0;         // first global particle index
+};
+
+struct Ctrl {          // device-resident step state, read by every kernel
+  uint64_t step;       // step index t of the next step
+  uint32_t cur;        // which state buffer holds the current state
+  uint32_t err;        // sticky error bits
+  int32_t reorder;     // R
+  uint32_t pad[3];
+};
+
+// State buffers of one form, SoA.  F64: a[0..2]=x (double), b[0..2]=v (double);
+// F32: x, v float; Split: cell (u32), a = offsets (float), b = v (float).
+struct StatePtrs {
+  void* a[3];
+  void* b[3];
+  uint32_t* cell;
+};
+
+struct Dev {           // device pointers carved from the workspace
+  StatePtrs S[2];
+  uint32_t* key;       // cell key per particle (storage order)
+  uint32_t* perm;      // sorted slot -> storage index
+  uint32_t* hist;      // particles per cell, zero between steps' scatter and collide
+  uint32_t* offset;    // exclusive prefix, ncell + 1
+  uint32_t* scan_blk;  // per scan-block totals
+  Ctrl* ctrl;
+  BoxDev* boxes;
+  Tile* tiles;
+  PBlock* pblocks;
+  double* partials;    // per-block observable partial sums
+  uint32_t ntot;       // particles over all boxes (bound of every particle index)
+};
+
+struct Launch {
+  int form;
+  uint32_t nbox;
+  uint64_t ntot, ctot;     // particles, cells over all boxes
+  uint32_t ntiles, npblocks, nscan;
+  uint32_t collide_grid;
+  int xcd_remap;
+  hipStream_t stream;
+};
+
+// Launchers (mpc_kernels.hip).
+hipError_t launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s);
+hipError_t launch_key_hist(const Dev& d, const Launch& l);
+hipError_t launch_scan(const Dev& d, const Launch& l);
+hipError_t launch_scatter(const Dev& d, const Launch& l);
+hipError_t launch_collide(const Dev& d, const Launch& l);
+hipError_t launch_advance(const Dev& d, const Launch& l);
+hipError_t launch_set_ctrl(const Dev& d, const Launch& l, uint64_t step, uint32_t cur,
+                           int32_t reorder, int clear_err);
+hipError_t launch_init_state(const Dev& d, const Launch& l, uint64_t seed);
+hipError_t launch_obs_pass1(const Dev& d, const Launch& l);
+hipError_t launch_obs_pass2(const Dev& d, const Launch& l, const double* vmean_dev);
+hipError_t launch_remove_mean(const Dev& d, const Launch& l, const double* vmean_dev);
+hipError_t launch_canon_perm(const Dev& d, const Launch& l);
+hipError_t collide_occupancy(int form, int* blocks_per_cu);
+
+}  // namespace mpc

@@ -1,0 +1,1352 @@
+// mpc_kernels.hip -- gfx950 kernels of the MPC-SRD step (arXiv:2406.15236, Sec. II).
+//
+// One step t on the device (steady state):
+//   scan    : offset = exclusive prefix of hist (particles per cell of step t)
+//   scatter : slot = offset[key] + atomicSub(hist[key]) - 1; perm[slot] = i
+//             (leaves hist at zero)
+//   collide : per tile of cells: gather the cell segments through perm, order
+//             each segment by storage index in LDS, stream (Eq. 1), sum the
+//             cells one thread per cell, draw axis / thermostat from Philox,
+//             rotate (Eq. 2) + scale, write the state (in place, or in cell
+//             order into the other buffer on reorder steps), and already
+//             stream + bin for step t+1: key[] and hist[] of the next step.
+//   advance : t += 1, flip the buffer after a reorder step.
+// The prologue kernel computes key/hist of step t when the state was set from
+// outside.  Every kernel reads the step index and buffer from Ctrl, so a
+// captured graph of one step can be replayed.
+#include <math.h>
+
+#include "mpc_internal.h"
+#include "philox_dev.h"
+
+namespace mpc {
+
+// ---------------------------------------------------------------------------
+// Random draws of the method
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ Words4 draw(const BoxDev& B, uint32_t j, uint32_t id, uint64_t t,
+                                       uint32_t tag) {
+  return philox10(j, id, (uint32_t)t, tag, B.key_lo, B.key_hi);
+}
+
+// Lattice shift of step t: s_k = u24(w_k) - 1/2 (exact 2^-24 grid).
+__device__ __forceinline__ void shift_of(const BoxDev& B, uint64_t t, double s[3]) {
+  const Words4 w = draw(B, 0, 0, t, kTagShift);
+  s[0] = u24_of(w.w[0]) - 0.5;
+  s[1] = u24_of(w.w[1]) - 0.5;
+  s[2] = u24_of(w.w[2]) - 0.5;
+}
+
+// Uniform random axis on the unit sphere: z = 1 - 2 u1, phi = 2 pi u2.
+__device__ __forceinline__ void axis_of(const BoxDev& B, uint64_t t, uint32_t key, double n[3]) {
+  const Words4 w = draw(B, 0, key, t, kTagAxis);
+  const double u1 = u53_of(w.w[0], w.w[1]);
+  const double u2 = u53_of(w.w[2], w.w[3]);
+  const double z = 1.0 - 2.0 * u1;
+  const double r = sqrt(1.0 - z * z);
+  const double phi = kTwoPi * u2;
+  double sp, cp;
+  sincos(phi, &sp, &cp);
+  n[0] = r * cp;
+  n[1] = r * sp;
+  n[2] = z;
+}
+
+// Gamma(shape, 1) by Marsaglia-Tsang; attempt j uses THERMO draw j
+// (Box-Muller cosine branch from words 0,1; acceptance uniform from 2,3).
+// Returns false if 64 attempts were rejected.
+__device__ __forceinline__ bool gamma_of(const BoxDev& B, uint64_t t, uint32_t key, double shape,
+                                      double* out) {
+  const double d = shape - 1.0 / 3.0;
+  const double c = 1.0 / sqrt(9.0 * d);
+#pragma unroll 1
+  for (uint32_t j = 0; j < 64; ++j) {
+    const Words4 w = draw(B, j, key, t, kTagThermo);
+    const double u1 = u32_open_of(w.w[0]);
+    const double u2 = (double)w.w[1] * 0x1p-32;
+    const double z = sqrt(-2.0 * log(u1)) * cos(kTwoPi * u2);
+    double vv = 1.0 + c * z;
+    if (vv <= 0.0) continue;
+    vv = vv * vv * vv;
+    const double u = u53_open_of(w.w[2], w.w[3]);
+    const double lhs = log(u);
+    const double rhs = 0.5 * z * z + d - d * vv + d * log(vv);
+    if (lhs < rhs) {
+      *out = d * vv;
+      return true;
+    }
+  }
+  return false;
+}
+
+// Phantom particles of a wall-cut cell: Poisson(<N_c> f_w) count by inversion
+// on draw 0, truncated at 127.
+__device__ __forceinline__ int phantom_count(const BoxDev& B, uint64_t t, uint32_t key, double fw) {
+  const double lam = B.density * fw;
+  const Words4 w = draw(B, 0, key, t, kTagPhantom);
+  const double u = u53_of(w.w[0], w.w[1]);
+  int k = 0;
+  double pk = exp(-lam);
+  double F = pk;
+#pragma unroll 1
+  while (u >= F && k < 127) {
+    k += 1;
+    pk = pk * lam / (double)k;
+    F = F + pk;
+  }
+  return k;
+}
+
+// Normal number m of a cell's phantom stream (draw 1 + m/4; Box-Muller pair
+// (m%4)/2; cosine for even m, sine for odd m).  `cache` keeps the last draw.
+struct PhantomCache {
+  uint32_t j;
+  Words4 w;
+};
+__device__ __forceinline__ double phantom_normal(const BoxDev& B, uint64_t t, uint32_t key,
+                                                 uint32_t m, PhantomCache& pc) {
+  const uint32_t j = 1 + m / 4;
+  if (pc.j != j) {
+    pc.w = draw(B, j, key, t, kTagPhantom);
+    pc.j = j;
+  }
+  const uint32_t pr = (m % 4) / 2;
+  const double r = sqrt(-2.0 * log(u32_open_of(pc.w.w[2 * pr])));
+  const double th = kTwoPi * ((double)pc.w.w[2 * pr + 1] * 0x1p-32);
+  return (m % 2 == 0) ? r * cos(th) : r * sin(th);
+}
+
+// Wall volume fraction of shifted z layer cz (layer spans [cz - sz, cz + 1 - sz)).
+__device__ __forceinline__ double wall_fraction(double sz, int cz, int H) {
+  if (sz >= 0.0) {
+    if (cz == 0) return sz;
+    if (cz == H) return 1.0 - sz;
+  } else {
+    if (cz == -1) return 1.0 + sz;
+    if (cz == H - 1) return -sz;
+  }
+  return 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Storage forms
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wrap64(double x, double L) {
+  if (x < 0.0) {
+    x = x + L;
+  } else if (x >= L) {
+    x = x - L;
+  }
+  if (!(x >= 0.0 && x < L)) {
+    if (x == L) {
+      x = 0.0;
+    } else if (isfinite(x)) {
+      x = x - L * floor(x / L);
+      if (x >= L || x < 0.0) x = 0.0;
+    }
+  }
+  return x;
+}
+
+__device__ __forceinline__ float wrap32(float x, float L) {
+  if (x < 0.0f) {
+    x = x + L;
+  } else if (x >= L) {
+    x = x - L;
+  }
+  if (!(x >= 0.0f && x < L)) {
+    if (x == L) {
+      x = 0.0f;
+    } else if (isfinite(x)) {
+      x = x - L * floorf(x / L);
+      if (x >= L || x < 0.0f) x = 0.0f;
+    }
+  }
+  return x;
+}
+
+// Eq.(1) in FP64 with periodic x, y and (walls) time-reversed bounce-back in z.
+__device__ __forceinline__ void stream_f64(double (&x)[3], double (&v)[3], const BoxDev& B) {
+  double xe = fma(B.h, v[0], x[0]);
+  double ye = fma(B.h, v[1], x[1]);
+  double ze = fma(B.h, v[2], x[2]);
+  if (B.walls) {
+    const double H = B.Ld[2];
+    const bool lo = ze < 0.0, hi = ze > H;
+    if (lo || hi) {
+      const double zw = lo ? 0.0 : H;
+      const double tr2 = 2.0 * ((ze - zw) / v[2]);
+      xe = xe - tr2 * v[0];
+      ye = ye - tr2 * v[1];
+      ze = ze - tr2 * v[2];
+      if (ze < 0.0) ze = 0.0;
+      if (ze > H) ze = H;
+      v[0] = -v[0];
+      v[1] = -v[1];
+      v[2] = -v[2];
+    }
+  } else {
+    ze = wrap64(ze, B.Ld[2]);
+  }
+  x[0] = wrap64(xe, B.Ld[0]);
+  x[1] = wrap64(ye, B.Ld[1]);
+  x[2] = ze;
+}
+
+__device__ __forceinline__ void stream_f32(float (&x)[3], float (&v)[3], const BoxDev& B) {
+  float xe = fmaf(B.hf, v[0], x[0]);
+  float ye = fmaf(B.hf, v[1], x[1]);
+  float ze = fmaf(B.hf, v[2], x[2]);
+  if (B.walls) {
+    const float H = B.Lf[2];
+    const bool lo = ze < 0.0f, hi = ze > H;
+    if (lo || hi) {
+      const float zw = lo ? 0.0f : H;
+      const float tr2 = 2.0f * ((ze - zw) / v[2]);
+      xe = xe - tr2 * v[0];
+      ye = ye - tr2 * v[1];
+      ze = ze - tr2 * v[2];
+      if (ze < 0.0f) ze = 0.0f;
+      if (ze > H) ze = H;
+      v[0] = -v[0];
+      v[1] = -v[1];
+      v[2] = -v[2];
+    }
+  } else {
+    ze = wrap32(ze, B.Lf[2]);
+  }
+  x[0] = wrap32(xe, B.Lf[0]);
+  x[1] = wrap32(ye, B.Lf[1]);
+  x[2] = ze;
+}
+
+// Split form: unshifted cell (packed) + offset in [0, 1) per axis.
+__device__ __forceinline__ void split_decode(uint32_t cell, int (&c)[3]) {
+  c[0] = (int)(cell & ((1u << kSplitXBits) - 1));
+  c[1] = (int)((cell >> kSplitXBits) & ((1u << kSplitYBits) - 1));
+  c[2] = (int)(cell >> (kSplitXBits + kSplitYBits));
+}
+__device__ __forceinline__ uint32_t split_encode(const int (&c)[3]) {
+  return (uint32_t)c[0] | ((uint32_t)c[1] << kSplitXBits) |
+         ((uint32_t)c[2] << (kSplitXBits + kSplitYBits));
+}
+__device__ __forceinline__ int wrap_cell(int c, int L) {
+  if (c < 0) {
+    c += L;
+  } else if (c >= L) {
+    c -= L;
+  }
+  if (c < 0 || c >= L) c = ((c % L) + L) % L;
+  return c;
+}
+// FP64 value -> (cell, offset) with the offset rounded to FP32.
+__device__ __forceinline__ void split_from_double(double xd, int& c, float& o) {
+  const double fl = floor(xd);
+  c = (int)fl;
+  o = (float)(xd - fl);
+  if (o >= 1.0f) {
+    o = 0.0f;
+    c += 1;
+  }
+}
+
+__device__ __forceinline__ void stream_split(uint32_t& cell, float (&o)[3], float (&v)[3],
+                                             const BoxDev& B) {
+  int c[3];
+  split_decode(cell, c);
+  int cn[3];
+  float on[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    float y = fmaf(B.hf, v[k], o[k]);
+    float fl = floorf(y);
+    y = y - fl;
+    if (y == 1.0f) {
+      y = 0.0f;
+      fl += 1.0f;
+    }
+    on[k] = y;
+    cn[k] = c[k] + (int)fl;
+  }
+  if (B.walls) {
+    const int H = B.L[2];
+    const bool out = cn[2] < 0 || cn[2] > H || (cn[2] == H && on[2] > 0.0f) ||
+                     !isfinite(on[2]);
+    if (out) {
+      // crossing particle: the bounce is done in FP64 from the exact position
+      double xd[3], vd[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        xd[k] = (double)c[k] + (double)o[k];
+        vd[k] = (double)v[k];
+      }
+      double xe[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) xe[k] = fma(B.h, vd[k], xd[k]);
+      const double Hd = B.Ld[2];
+      if (xe[2] < 0.0 || xe[2] > Hd) {
+        const double zw = xe[2] < 0.0 ? 0.0 : Hd;
+        const double tr2 = 2.0 * ((xe[2] - zw) / vd[2]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xe[k] = xe[k] - tr2 * vd[k];
+        if (xe[2] < 0.0) xe[2] = 0.0;
+        if (xe[2] > Hd) xe[2] = Hd;
+        v[0] = -v[0];
+        v[1] = -v[1];
+        v[2] = -v[2];
+      }
+      xe[0] = wrap64(xe[0], B.Ld[0]);
+      xe[1] = wrap64(xe[1], B.Ld[1]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) split_from_double(xe[k], cn[k], on[k]);
+    }
+  } else {
+    cn[2] = wrap_cell(cn[2], B.L[2]);
+  }
+  cn[0] = wrap_cell(cn[0], B.L[0]);
+  cn[1] = wrap_cell(cn[1], B.L[1]);
+  o[0] = on[0];
+  o[1] = on[1];
+  o[2] = on[2];
+  cell = split_encode(cn);
+}
+
+// Key of shifted cell coordinates c_k = floor(x_k + s_k) (x_k given as
+// integer part ci_k plus fraction xf_k in double; exact).  Invalid -> err.
+__device__ __forceinline__ uint32_t key_of(const int (&ci)[3], const double (&xf)[3],
+                                           const double (&s)[3], const BoxDev& B, uint32_t& err) {
+  int c[3];
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double y = xf[k] + s[k];
+    if (!(y >= -2.0 && y < (double)B.L[k] + 2.0)) {
+      ok = false;
+      c[k] = 0;
+    } else {
+      c[k] = ci[k] + (int)floor(y);
+    }
+  }
+  if (ok) {
+    c[0] = c[0] < 0 ? c[0] + B.L[0] : (c[0] >= B.L[0] ? c[0] - B.L[0] : c[0]);
+    c[1] = c[1] < 0 ? c[1] + B.L[1] : (c[1] >= B.L[1] ? c[1] - B.L[1] : c[1]);
+    if (B.walls) {
+      c[2] += 1;
+    } else {
+      c[2] = c[2] < 0 ? c[2] + B.L[2] : (c[2] >= B.L[2] ? c[2] - B.L[2] : c[2]);
+    }
+    ok = c[0] >= 0 && c[0] < B.L[0] && c[1] >= 0 && c[1] < B.L[1] && c[2] >= 0 &&
+         c[2] < B.nlz;
+  }
+  if (!ok) {
+    err |= kErrKey;
+    return 0;
+  }
+  return (uint32_t)((c[2] * B.L[1] + c[1]) * B.L[0] + c[0]);
+}
+
+// Per-form particle access.  P = position type, V = velocity type,
+// Vs = LDS velocity type, R = rotation arithmetic type.
+template <int F>
+struct Form;
+
+template <>
+struct Form<kFormF64> {
+  struct P {
+    double x[3];
+  };
+  struct Vv {
+    double v[3];
+  };
+  using Vs = double;
+  using Xs = double;
+  static constexpr bool kHasCell = false;
+  __device__ static void to_lds(const P& p, Xs* x0, Xs* x1, Xs* x2, uint32_t*, uint32_t q) {
+    x0[q] = p.x[0];
+    x1[q] = p.x[1];
+    x2[q] = p.x[2];
+  }
+  __device__ static void from_lds(P& p, const Xs* x0, const Xs* x1, const Xs* x2,
+                                  const uint32_t*, uint32_t q) {
+    p.x[0] = x0[q];
+    p.x[1] = x1[q];
+    p.x[2] = x2[q];
+  }
+  __device__ static void load(const StatePtrs& S, uint32_t i, P& p, Vv& v) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      p.x[k] = ((const double*)S.a[k])[i];
+      v.v[k] = ((const double*)S.b[k])[i];
+    }
+  }
+  __device__ static void store(const StatePtrs& S, uint32_t j, const P& p, const Vv& v) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ((double*)S.a[k])[j] = p.x[k];
+      ((double*)S.b[k])[j] = v.v[k];
+    }
+  }
+  __device__ static void stream(P& p, Vv& v, const BoxDev& B) { stream_f64(p.x, v.v, B); }
+  __device__ static uint32_t key(const P& p, const double (&s)[3], const BoxDev& B,
+                                 uint32_t& err) {
+    const int ci[3] = {0, 0, 0};
+    const double xf[3] = {p.x[0], p.x[1], p.x[2]};
+    return key_of(ci, xf, s, B, err);
+  }
+};
+
+template <>
+struct Form<kFormF32> {
+  struct P {
+    float x[3];
+  };
+  struct Vv {
+    float v[3];
+  };
+  using Vs = float;
+  using Xs = float;
+  static constexpr bool kHasCell = false;
+  __device__ static void to_lds(const P& p, Xs* x0, Xs* x1, Xs* x2, uint32_t*, uint32_t q) {
+    x0[q] = p.x[0];
+    x1[q] = p.x[1];
+    x2[q] = p.x[2];
+  }
+  __device__ static void from_lds(P& p, const Xs* x0, const Xs* x1, const Xs* x2,
+                                  const uint32_t*, uint32_t q) {
+    p.x[0] = x0[q];
+    p.x[1] = x1[q];
+    p.x[2] = x2[q];
+  }
+  __device__ static void load(const StatePtrs& S, uint32_t i, P& p, Vv& v) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      p.x[k] = ((const float*)S.a[k])[i];
+      v.v[k] = ((const float*)S.b[k])[i];
+    }
+  }
+  __device__ static void store(const StatePtrs& S, uint32_t j, const P& p, const Vv& v) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ((float*)S.a[k])[j] = p.x[k];
+      ((float*)S.b[k])[j] = v.v[k];
+    }
+  }
+  __device__ static void stream(P& p, Vv& v, const BoxDev& B) { stream_f32(p.x, v.v, B); }
+  __device__ static uint32_t key(const P& p, const double (&s)[3], const BoxDev& B,
+                                 uint32_t& err) {
+    const int ci[3] = {0, 0, 0};
+    const double xf[3] = {(double)p.x[0], (double)p.x[1], (double)p.x[2]};
+    return key_of(ci, xf, s, B, err);
+  }
+};
+
+template <>
+struct Form<kFormSplit> {
+  struct P {
+    uint32_t cell;
+    float o[3];
+  };
+  struct Vv {
+    float v[3];
+  };
+  using Vs = float;
+  using Xs = float;
+  static constexpr bool kHasCell = true;
+  __device__ static void to_lds(const P& p, Xs* x0, Xs* x1, Xs* x2, uint32_t* c, uint32_t q) {
+    x0[q] = p.o[0];
+    x1[q] = p.o[1];
+    x2[q] = p.o[2];
+    c[q] = p.cell;
+  }
+  __device__ static void from_lds(P& p, const Xs* x0, const Xs* x1, const Xs* x2,
+                                  const uint32_t* c, uint32_t q) {
+    p.o[0] = x0[q];
+    p.o[1] = x1[q];
+    p.o[2] = x2[q];
+    p.cell = c[q];
+  }
+  __device__ static void load(const StatePtrs& S, uint32_t i, P& p, Vv& v) {
+    p.cell = S.cell[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      p.o[k] = ((const float*)S.a[k])[i];
+      v.v[k] = ((const float*)S.b[k])[i];
+    }
+  }
+  __device__ static void store(const StatePtrs& S, uint32_t j, const P& p, const Vv& v) {
+    S.cell[j] = p.cell;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ((float*)S.a[k])[j] = p.o[k];
+      ((float*)S.b[k])[j] = v.v[k];
+    }
+  }
+  __device__ static void stream(P& p, Vv& v, const BoxDev& B) {
+    stream_split(p.cell, p.o, v.v, B);
+  }
+  __device__ static uint32_t key(const P& p, const double (&s)[3], const BoxDev& B,
+                                 uint32_t& err) {
+    int ci[3];
+    split_decode(p.cell, ci);
+    const double xf[3] = {(double)p.o[0], (double)p.o[1], (double)p.o[2]};
+    return key_of(ci, xf, s, B, err);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Small kernels
+// ---------------------------------------------------------------------------
+__global__ void k_zero_u32(uint32_t* p, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
+__global__ void k_set_ctrl(Ctrl* c, uint64_t step, uint32_t cur, int32_t reorder, int clear_err) {
+  c->step = step;
+  c->cur = cur;
+  c->reorder = reorder;
+  if (clear_err) c->err = 0u;
+}
+
+__global__ void k_advance(Ctrl* c) {
+  const uint64_t t = c->step;
+  const int32_t R = c->reorder;
+  if (R > 0 && (t + 1) % (uint64_t)R == 0) c->cur ^= 1u;
+  c->step = t + 1;
+}
+
+// Prologue: key and histogram of step t from the current state.
+template <int F>
+__global__ __launch_bounds__(kThreads) void k_key_hist(Dev d) {
+  using Fm = Form<F>;
+  __shared__ double s_sh[3];
+  const PBlock pb = d.pblocks[blockIdx.x];
+  const BoxDev& B = d.boxes[pb.box];
+  const uint64_t t = d.ctrl->step;
+  const StatePtrs S = d.S[d.ctrl->cur];
+  if (threadIdx.x == 0) {
+    double s[3];
+    shift_of(B, t, s);
+    s_sh[0] = s[0];
+    s_sh[1] = s[1];
+    s_sh[2] = s[2];
+  }
+  __syncthreads();
+  const double s[3] = {s_sh[0], s_sh[1], s_sh[2]};
+  const uint32_t pend = B.pbase + B.np;
+  uint32_t err = 0;
+#pragma unroll
+  for (int k = 0; k < kPartBlock / kThreads; ++k) {
+    const uint32_t i = pb.p0 + k * kThreads + threadIdx.x;
+    if (i < pend) {
+      typename Fm::P p;
+      typename Fm::Vv v;
+      Fm::load(S, i, p, v);
+      Fm::stream(p, v, B);
+      const uint32_t key = B.cbase + Fm::key(p, s, B, err);
+      d.key[i] = key;
+      atomicAdd(&d.hist[key], 1u);
+    }
+  }
+  if (err) atomicOr(&d.ctrl->err, err);
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan of hist -> offset (reduce, top, down-sweep)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int dlt = 1; dlt < 64; dlt <<= 1) {
+    const uint32_t y = __shfl_up(x, dlt, 64);
+    if (lane >= dlt) x += y;
+  }
+  return x;
+}
+
+// Exclusive block scan of one value per thread; returns the block total too.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s_w,
+                                                         uint32_t& total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const uint32_t inc = wave_inclusive_scan(x);
+  if (lane == 63) s_w[wid] = inc;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+  for (int w = 0; w < nw; ++w) {
+    const uint32_t sw = s_w[w];
+    if (w < wid) pre += sw;
+    tot += sw;
+  }
+  total = tot;
+  __syncthreads();
+  return pre + inc - x;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t* __restrict__ hist,
+                                                          uint32_t* __restrict__ blk) {
+  __shared__ uint32_t s_w[kThreads / 64];
+  const uint4* h4 = (const uint4*)(hist + (uint64_t)blockIdx.x * kScanBlock);
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems / 4; ++k) {
+    const uint4 q = h4[k * kThreads + threadIdx.x];
+    sum += q.x + q.y + q.z + q.w;
+  }
+  uint32_t total;
+  block_exclusive_scan(sum, s_w, total);
+  if (threadIdx.x == 0) blk[blockIdx.x] = total;
+}
+
+// One workgroup of 1024 threads scans all block totals in place (exclusive).
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ blk, uint32_t nblk) {
+  __shared__ uint32_t s_w[16];
+  __shared__ uint32_t s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < nblk; base += 1024) {
+    const uint32_t i = base + threadIdx.x;
+    const uint32_t x = i < nblk ? blk[i] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(x, s_w, total);
+    const uint32_t carry = s_carry;
+    if (i < nblk) blk[i] = carry + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry = carry + total;
+    __syncthreads();
+  }
+}
+
+// Each thread owns kScanItems consecutive cells.
+__global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t* __restrict__ hist,
+                                                        const uint32_t* __restrict__ blk,
+                                                        uint32_t* __restrict__ offset,
+                                                        uint32_t nblk) {
+  __shared__ uint32_t s_w[kThreads / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanItems;
+  const uint4* h4 = (const uint4*)(hist + base);
+  uint32_t v[kScanItems];
+#pragma unroll
+  for (int k = 0; k < kScanItems / 4; ++k) {
+    const uint4 q = h4[k];
+    v[4 * k] = q.x;
+    v[4 * k + 1] = q.y;
+    v[4 * k + 2] = q.z;
+    v[4 * k + 3] = q.w;
+  }
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) sum += v[k];
+  uint32_t total;
+  uint32_t run = blk[blockIdx.x] + block_exclusive_scan(sum, s_w, total);
+  uint4* o4 = (uint4*)(offset + base);
+#pragma unroll
+  for (int k = 0; k < kScanItems / 4; ++k) {
+    uint4 q;
+    q.x = run;
+    run += v[4 * k];
+    q.y = run;
+    run += v[4 * k + 1];
+    q.z = run;
+    run += v[4 * k + 2];
+    q.w = run;
+    run += v[4 * k + 3];
+    o4[k] = q;
+  }
+  if (blockIdx.x == nblk - 1 && threadIdx.x == kThreads - 1)
+    offset[(uint64_t)nblk * kScanBlock] = run;
+}
+
+// ---------------------------------------------------------------------------
+// Scatter: slot of each particle inside its cell segment (order inside a
+// segment is arbitrary here and made canonical in collide).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict__ key,
+                                                      uint32_t* __restrict__ hist,
+                                                      const uint32_t* __restrict__ offset,
+                                                      uint32_t* __restrict__ perm, uint32_t n,
+                                                      uint32_t ncell, Ctrl* ctrl) {
+  uint32_t bad = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t i = blockIdx.x * (kThreads * 4) + k * kThreads + threadIdx.x;
+    if (i < n) {
+      const uint32_t c = key[i];
+      if (c >= ncell) {
+        bad = 1;
+        continue;
+      }
+      const uint32_t old = atomicSub(&hist[c], 1u);
+      const uint32_t slot = offset[c] + old - 1u;
+      if (old == 0u || slot >= n) {
+        bad = 1;
+        continue;
+      }
+      perm[slot] = i;
+    }
+  }
+  if (bad) atomicOr(&ctrl->err, kErrKey);
+}
+
+// ---------------------------------------------------------------------------
+// Collide (+ stream/bin of the next step)
+// ---------------------------------------------------------------------------
+struct CellLds {
+  double V[3];
+  double n[3];
+  double kappa;
+  uint32_t active;
+  uint32_t pad;
+};
+
+// Sums and random draws of one cell, one thread per cell.  Velocities of the
+// cell's fluid particles are sv[k][b..e) in canonical order.
+template <int F>
+__device__ void cell_work(const BoxDev& B, uint64_t t, uint32_t lkey, double sz,
+                          const typename Form<F>::Vs* __restrict__ sv0,
+                          const typename Form<F>::Vs* __restrict__ sv1,
+                          const typename Form<F>::Vs* __restrict__ sv2, uint32_t b, uint32_t e,
+                          CellLds& out) {
+  const uint32_t nf = e - b;
+  out.active = 0u;
+  out.kappa = 1.0;
+  if (nf == 0) return;
+  int nph = 0;
+  double fw = 0.0;
+  if (B.walls) {
+    const int cz = (int)(lkey / (uint32_t)(B.L[0] * B.L[1])) - 1;
+    fw = wall_fraction(sz, cz, B.L[2]);
+    if (fw > 0.0) nph = phantom_count(B, t, lkey, fw);
+  }
+  const uint32_t ntot = nf + (uint32_t)nph;
+  const double m = B.mass;
+  double V[3];
+  if constexpr (F == kFormSplit) {
+    // compensated FP32 momentum sums (Neumaier)
+    const float mf = (float)m;
+    float s[3] = {0.f, 0.f, 0.f}, c[3] = {0.f, 0.f, 0.f};
+    auto add = [&](int k, float x) {
+      const float tt = s[k] + x;
+      if (fabsf(s[k]) >= fabsf(x)) {
+        c[k] += (s[k] - tt) + x;
+      } else {
+        c[k] += (x - tt) + s[k];
+      }
+      s[k] = tt;
+    };
+#pragma unroll 1
+    for (uint32_t q = b; q < e; ++q) {
+      add(0, mf * sv0[q]);
+      add(1, mf * sv1[q]);
+      add(2, mf * sv2[q]);
+    }
+    if (nph) {
+      PhantomCache pc;
+      pc.j = 0xffffffffu;
+#pragma unroll 1
+      for (int q = 0; q < nph; ++q)
+#pragma unroll 1
+        for (int k = 0; k < 3; ++k)
+          add(k, mf * (float)(B.sd * phantom_normal(B, t, lkey, 3 * q + k, pc)));
+    }
+    const float Mf = (float)ntot * mf;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) V[k] = (double)((s[k] + c[k]) / Mf);
+  } else {
+    double P[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (uint32_t q = b; q < e; ++q) {
+      P[0] = P[0] + m * (double)sv0[q];
+      P[1] = P[1] + m * (double)sv1[q];
+      P[2] = P[2] + m * (double)sv2[q];
+    }
+    if (nph) {
+      PhantomCache pc;
+      pc.j = 0xffffffffu;
+#pragma unroll 1
+      for (int q = 0; q < nph; ++q)
+#pragma unroll 1
+        for (int k = 0; k < 3; ++k)
+          P[k] = P[k] + m * (B.sd * phantom_normal(B, t, lkey, 3 * q + k, pc));
+    }
+    const double M = (double)ntot * m;
+    V[0] = P[0] / M;
+    V[1] = P[1] / M;
+    V[2] = P[2] / M;
+  }
+  out.V[0] = V[0];
+  out.V[1] = V[1];
+  out.V[2] = V[2];
+  if (ntot < 2) return;
+  out.active = 1u;
+  axis_of(B, t, lkey, out.n);
+  if (B.mbs) {
+    double K = 0.0;
+#pragma unroll 1
+    for (uint32_t q = b; q < e; ++q) {
+      const double dx = (double)sv0[q] - V[0], dy = (double)sv1[q] - V[1],
+                   dz = (double)sv2[q] - V[2];
+      K = K + m * (dx * dx + dy * dy + dz * dz);
+    }
+    if (nph) {
+      PhantomCache pc;
+      pc.j = 0xffffffffu;
+#pragma unroll 1
+      for (int q = 0; q < nph; ++q) {
+        double d2[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          double vp = B.sd * phantom_normal(B, t, lkey, 3 * q + k, pc);
+          if constexpr (F == kFormSplit) vp = (double)(float)vp;
+          d2[k] = vp - V[k];
+        }
+        K = K + m * (d2[0] * d2[0] + d2[1] * d2[1] + d2[2] * d2[2]);
+      }
+    }
+    if (K > 0.0) {
+      double gv;
+      if (gamma_of(B, t, lkey, 1.5 * (double)(ntot - 1), &gv)) {
+        const double Ek = B.kT * gv;
+        out.kappa = sqrt((2.0 * Ek) / K);
+      }
+    }
+  }
+}
+
+template <int F>
+__global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
+  using Fm = Form<F>;
+  using Vs = typename Fm::Vs;
+  using Xs = typename Fm::Xs;
+  constexpr int NT = kCollideThreads;
+  constexpr int NS = kTileCap / kCollideThreads;
+  static_assert(kTileMaxCells <= NT, "one thread per cell of a tile");
+  __shared__ uint32_t s_off[kTileMaxCells + 1];
+  __shared__ uint32_t s_idx[kTileCap];   // perm entries, segment order as scattered
+  __shared__ uint32_t s_idxc[kTileCap];  // storage index at the canonical position
+  __shared__ uint8_t s_lc[kTileCap];     // local cell of each slot
+  __shared__ Vs s_v[3][kTileCap];        // streamed velocities, canonical order
+  __shared__ Xs s_x[3][kTileCap];        // streamed positions (offsets), canonical order
+  __shared__ uint32_t s_c[Fm::kHasCell ? kTileCap : 1];
+  __shared__ CellLds s_cell[kTileMaxCells];
+  __shared__ double s_sh[6];
+
+  const uint64_t t = d.ctrl->step;
+  const uint32_t cur = d.ctrl->cur;
+  const int32_t R = d.ctrl->reorder;
+  const bool sorted = R > 0 && (t + 1) % (uint64_t)R == 0;
+  const StatePtrs in = d.S[cur];
+  const StatePtrs out = sorted ? d.S[cur ^ 1u] : d.S[cur];
+  uint32_t err = 0;
+
+  // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a
+  // contiguous range of tiles so that neighbouring rows share its L2.
+  const uint32_t G = gridDim.x;
+  uint32_t first = blockIdx.x, stride = G;
+  uint32_t per_xcd = 0, xcd = 0;
+  if (xcd_remap && G % 8 == 0) {
+    xcd = blockIdx.x % 8;
+    per_xcd = (ntiles + 7) / 8;
+    first = blockIdx.x / 8;
+    stride = G / 8;
+  }
+  uint32_t cached_box = 0xffffffffu;
+
+  for (uint32_t it = first;; it += stride) {
+    uint32_t tile;
+    if (per_xcd) {
+      if (it >= per_xcd) break;
+      tile = xcd * per_xcd + it;
+      if (tile >= ntiles) break;
+    } else {
+      if (it >= ntiles) break;
+      tile = it;
+    }
+    const Tile T = d.tiles[tile];
+    const BoxDev& B = d.boxes[T.box];
+    __syncthreads();  // LDS of the previous tile is free
+    if (threadIdx.x <= T.nc) s_off[threadIdx.x] = d.offset[T.c0 + threadIdx.x];
+    if (threadIdx.x == 0 && T.box != cached_box) {
+      double s0[3], s1[3];
+      shift_of(B, t, s0);
+      shift_of(B, t + 1, s1);
+      s_sh[0] = s0[0];
+      s_sh[1] = s0[1];
+      s_sh[2] = s0[2];
+      s_sh[3] = s1[0];
+      s_sh[4] = s1[1];
+      s_sh[5] = s1[2];
+    }
+    cached_box = T.box;
+    __syncthreads();
+    const uint32_t lkey0 = T.c0 - B.cbase;
+
+    uint32_t cs = 0;
+    while (cs < T.nc) {
+      const uint32_t base = s_off[cs];
+      // largest ce in (cs, nc] with s_off[ce] - base <= capacity
+      uint32_t ce;
+      if (s_off[T.nc] - base <= (uint32_t)kTileCap) {
+        ce = T.nc;
+      } else {
+        uint32_t lo = cs + 1, hi = T.nc;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) / 2;
+          if (s_off[mid] - base <= (uint32_t)kTileCap) {
+            lo = mid;
+          } else {
+            hi = mid;
+          }
+        }
+        ce = lo;
+      }
+      if (s_off[ce] < base || s_off[ce] > d.ntot) {  // inconsistent offsets: stop
+        err |= kErrKey;
+        break;
+      }
+      const uint32_t np = s_off[ce] - base;
+
+      if (np > (uint32_t)kTileCap) {
+        // one cell beyond capacity: stream and re-bin its particles unchanged
+        err |= kErrCellOverflow;
+        const double snx[3] = {s_sh[3], s_sh[4], s_sh[5]};
+        for (uint32_t q = threadIdx.x; q < np; q += NT) {
+          const uint32_t i = d.perm[base + q];
+          if (i >= d.ntot) continue;
+          typename Fm::P p;
+          typename Fm::Vv v;
+          Fm::load(in, i, p, v);
+          Fm::stream(p, v, B);
+          const uint32_t j = sorted ? base + q : i;
+          Fm::store(out, j, p, v);
+          Fm::stream(p, v, B);
+          const uint32_t kn = B.cbase + Fm::key(p, snx, B, err);
+          d.key[j] = kn;
+          atomicAdd(&d.hist[kn], 1u);
+        }
+        cs = ce;
+        __syncthreads();
+        continue;
+      }
+
+      // Phase A: segment entries and their local cell
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const uint32_t q = threadIdx.x + k * NT;
+        if (q < np) s_idx[q] = d.perm[base + q];
+      }
+      if (cs + threadIdx.x < ce) {
+        const uint32_t c = cs + threadIdx.x;
+        const uint32_t b = s_off[c] - base, e = s_off[c + 1] - base;
+        for (uint32_t q = b; q < e; ++q) s_lc[q] = (uint8_t)(c - cs);
+      }
+      __syncthreads();
+
+      // Phase B: gather, canonical position (rank by storage index inside
+      // the cell), stream of step t, park in LDS.  All gathers are issued
+      // first; the slots are then finished one after the other.
+      {
+        typename Fm::P p[NS];
+        typename Fm::Vv v[NS];
+        uint32_t ii[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const uint32_t q = threadIdx.x + k * NT;
+          ii[k] = 0;
+          if (q < np) {
+            ii[k] = s_idx[q] < d.ntot ? s_idx[q] : 0u;
+            Fm::load(in, ii[k], p[k], v[k]);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const uint32_t q = threadIdx.x + k * NT;
+          __builtin_amdgcn_sched_barrier(0);
+          if (q < np) {
+            const uint32_t i = ii[k];
+            const uint32_t c = cs + s_lc[q];
+            const uint32_t b = s_off[c] - base, e = s_off[c + 1] - base;
+            uint32_t r = 0;
+            for (uint32_t q2 = b; q2 < e; ++q2) r += s_idx[q2] < i ? 1u : 0u;
+            const uint32_t qc = b + r;
+            Fm::stream(p[k], v[k], B);
+            Fm::to_lds(p[k], s_x[0], s_x[1], s_x[2], s_c, qc);
+            s_v[0][qc] = v[k].v[0];
+            s_v[1][qc] = v[k].v[1];
+            s_v[2][qc] = v[k].v[2];
+            s_idxc[qc] = i;
+          }
+        }
+      }
+      __syncthreads();
+
+      // Phase C: one thread per cell
+      if (cs + threadIdx.x < ce) {
+        const uint32_t c = cs + threadIdx.x;
+        const uint32_t b = s_off[c] - base, e = s_off[c + 1] - base;
+        cell_work<F>(B, t, lkey0 + c, s_sh[2], s_v[0], s_v[1], s_v[2], b, e, s_cell[c - cs]);
+      }
+      __syncthreads();
+
+      // Phase D: rotate + scale, gravity, write, stream + bin step t+1
+      const double snext[3] = {s_sh[3], s_sh[4], s_sh[5]};
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const uint32_t q = threadIdx.x + k * NT;
+        __builtin_amdgcn_sched_barrier(0);
+        if (q < np) {
+          typename Fm::P p;
+          typename Fm::Vv v;
+          Fm::from_lds(p, s_x[0], s_x[1], s_x[2], s_c, q);
+          v.v[0] = s_v[0][q];
+          v.v[1] = s_v[1][q];
+          v.v[2] = s_v[2][q];
+          const CellLds& C = s_cell[s_lc[q]];
+          if constexpr (F == kFormSplit) {
+            if (C.active) {
+              const float V[3] = {(float)C.V[0], (float)C.V[1], (float)C.V[2]};
+              const float n[3] = {(float)C.n[0], (float)C.n[1], (float)C.n[2]};
+              const float ca = (float)B.ca, sa = (float)B.sa, omc = (float)B.omc;
+              const float kap = (float)C.kappa;
+              const float u[3] = {v.v[0] - V[0], v.v[1] - V[1], v.v[2] - V[2]};
+              const float ndu = n[0] * u[0] + n[1] * u[1] + n[2] * u[2];
+              const float cr[3] = {n[1] * u[2] - n[2] * u[1], n[2] * u[0] - n[0] * u[2],
+                                   n[0] * u[1] - n[1] * u[0]};
+              const float f = omc * ndu;
+#pragma unroll
+              for (int a = 0; a < 3; ++a)
+                v.v[a] = V[a] + kap * (ca * u[a] + sa * cr[a] + f * n[a]);
+            }
+            if (B.grav) {
+#pragma unroll
+              for (int a = 0; a < 3; ++a) v.v[a] = v.v[a] + (float)B.gh[a];
+            }
+          } else {
+            double w[3] = {(double)v.v[0], (double)v.v[1], (double)v.v[2]};
+            if (C.active) {
+              const double u[3] = {w[0] - C.V[0], w[1] - C.V[1], w[2] - C.V[2]};
+              const double ndu = C.n[0] * u[0] + C.n[1] * u[1] + C.n[2] * u[2];
+              const double cr[3] = {C.n[1] * u[2] - C.n[2] * u[1],
+                                    C.n[2] * u[0] - C.n[0] * u[2],
+                                    C.n[0] * u[1] - C.n[1] * u[0]};
+              const double f = B.omc * ndu;
+#pragma unroll
+              for (int a = 0; a < 3; ++a) {
+                const double up = B.ca * u[a] + B.sa * cr[a] + f * C.n[a];
+                w[a] = C.V[a] + C.kappa * up;
+              }
+            }
+            if (B.grav) {
+#pragma unroll
+              for (int a = 0; a < 3; ++a) w[a] = w[a] + B.gh[a];
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) v.v[a] = (Vs)w[a];
+          }
+          const uint32_t j = sorted ? base + q : s_idxc[q];
+          if (j >= d.ntot) {
+            err |= kErrKey;
+            continue;
+          }
+          Fm::store(out, j, p, v);
+          Fm::stream(p, v, B);
+          const uint32_t kn = B.cbase + Fm::key(p, snext, B, err);
+          d.key[j] = kn;
+          atomicAdd(&d.hist[kn], 1u);
+        }
+      }
+      cs = ce;
+      __syncthreads();
+    }
+  }
+  if (err) atomicOr(&d.ctrl->err, err);
+}
+
+hipError_t collide_occupancy(int form, int* blocks_per_cu) {
+  switch (form) {
+    case kFormF64:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_collide<kFormF64>,
+                                                          kCollideThreads, 0);
+    case kFormF32:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_collide<kFormF32>,
+                                                          kCollideThreads, 0);
+    default:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_collide<kFormSplit>,
+                                                          kCollideThreads, 0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Canonical permutation for export: sort each cell segment by storage index.
+// ---------------------------------------------------------------------------
+__global__ void k_canon_perm(uint32_t* __restrict__ perm, const uint32_t* __restrict__ offset,
+                             uint64_t ncell, uint32_t n) {
+  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const uint32_t b = offset[c], e = offset[c + 1];
+  if (e > n || b > e) return;
+  for (uint32_t i = b + 1; i < e; ++i) {
+    const uint32_t x = perm[i];
+    uint32_t j = i;
+    while (j > b && perm[j - 1] > x) {
+      perm[j] = perm[j - 1];
+      --j;
+    }
+    perm[j] = x;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Device init: positions uniform, velocities normal (INIT streams keyed by
+// the init seed; counter {draw, particle, box, tag}).
+// ---------------------------------------------------------------------------
+template <int F>
+__global__ __launch_bounds__(kThreads) void k_init_state(Dev d, uint32_t k0, uint32_t k1) {
+  const PBlock pb = d.pblocks[blockIdx.x];
+  const BoxDev& B = d.boxes[pb.box];
+  const StatePtrs S = d.S[d.ctrl->cur];
+  const uint32_t pend = B.pbase + B.np;
+  for (int s = 0; s < kPartBlock / kThreads; ++s) {
+    const uint32_t i = pb.p0 + s * kThreads + threadIdx.x;
+    if (i >= pend) continue;
+    const uint32_t li = i - B.pbase;
+    const Words4 a = philox10(0, li, pb.box, kTagInitPos, k0, k1);
+    const Words4 b = philox10(1, li, pb.box, kTagInitPos, k0, k1);
+    double x[3] = {u53_of(a.w[0], a.w[1]) * B.Ld[0], u53_of(a.w[2], a.w[3]) * B.Ld[1],
+                   u53_of(b.w[0], b.w[1]) * B.Ld[2]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (x[k] >= B.Ld[k]) x[k] = nextafter(B.Ld[k], 0.0);
+    const Words4 c = philox10(0, li, pb.box, kTagInitVel, k0, k1);
+    const double r0 = sqrt(-2.0 * log(u32_open_of(c.w[0])));
+    const double r1 = sqrt(-2.0 * log(u32_open_of(c.w[2])));
+    const double t0 = kTwoPi * ((double)c.w[1] * 0x1p-32);
+    const double t1 = kTwoPi * ((double)c.w[3] * 0x1p-32);
+    const double v[3] = {B.sd * r0 * cos(t0), B.sd * r0 * sin(t0), B.sd * r1 * cos(t1)};
+    if constexpr (F == kFormF64) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        ((double*)S.a[k])[i] = x[k];
+        ((double*)S.b[k])[i] = v[k];
+      }
+    } else if constexpr (F == kFormF32) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        float xf = (float)x[k];
+        if (xf >= B.Lf[k]) xf = nextafterf(B.Lf[k], 0.0f);
+        ((float*)S.a[k])[i] = xf;
+        ((float*)S.b[k])[i] = (float)v[k];
+      }
+    } else {
+      int c3[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        float o;
+        split_from_double(x[k], c3[k], o);
+        if (c3[k] >= B.L[k]) {
+          c3[k] = B.L[k] - 1;
+          o = nextafterf(1.0f, 0.0f);
+        }
+        ((float*)S.a[k])[i] = o;
+        ((float*)S.b[k])[i] = (float)v[k];
+      }
+      S.cell[i] = split_encode(c3);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Observables: per-block partial sums (FP64), reduced on the host side of the
+// call in block order.  pass 1: P (3), E; pass 2: sum m |v - vmean|^2.
+// ---------------------------------------------------------------------------
+template <int F>
+__device__ __forceinline__ void load_vel_d(const StatePtrs& S, uint32_t i, double (&v)[3]) {
+  if constexpr (F == kFormF64) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = ((const double*)S.b[k])[i];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = (double)((const float*)S.b[k])[i];
+  }
+}
+
+__device__ __forceinline__ double block_sum_d(double x, double* s_red) {
+  // deterministic tree sum over the block (fixed order)
+  s_red[threadIdx.x] = x;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s_red[threadIdx.x] = s_red[threadIdx.x] + s_red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = s_red[0];
+  __syncthreads();
+  return r;
+}
+
+template <int F>
+__global__ __launch_bounds__(kThreads) void k_obs_pass1(Dev d) {
+  __shared__ double s_red[kThreads];
+  const PBlock pb = d.pblocks[blockIdx.x];
+  const BoxDev& B = d.boxes[pb.box];
+  const StatePtrs S = d.S[d.ctrl->cur];
+  const uint32_t pend = B.pbase + B.np;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < kPartBlock / kThreads; ++s) {
+    const uint32_t i = pb.p0 + s * kThreads + threadIdx.x;
+    if (i >= pend) continue;
+    double v[3];
+    load_vel_d<F>(S, i, v);
+    acc[0] += B.mass * v[0];
+    acc[1] += B.mass * v[1];
+    acc[2] += B.mass * v[2];
+    acc[3] += 0.5 * B.mass * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  }
+  for (int k = 0; k < 4; ++k) {
+    const double r = block_sum_d(acc[k], s_red);
+    if (threadIdx.x == 0) d.partials[(uint64_t)blockIdx.x * 4 + k] = r;
+  }
+}
+
+template <int F>
+__global__ __launch_bounds__(kThreads) void k_obs_pass2(Dev d, const double* vmean) {
+  __shared__ double s_red[kThreads];
+  const PBlock pb = d.pblocks[blockIdx.x];
+  const BoxDev& B = d.boxes[pb.box];
+  const StatePtrs S = d.S[d.ctrl->cur];
+  const uint32_t pend = B.pbase + B.np;
+  const double V[3] = {vmean[3 * pb.box], vmean[3 * pb.box + 1], vmean[3 * pb.box + 2]};
+  double acc = 0.0;
+  for (int s = 0; s < kPartBlock / kThreads; ++s) {
+    const uint32_t i = pb.p0 + s * kThreads + threadIdx.x;
+    if (i >= pend) continue;
+    double v[3];
+    load_vel_d<F>(S, i, v);
+    const double dx = v[0] - V[0], dy = v[1] - V[1], dz = v[2] - V[2];
+    acc += B.mass * (dx * dx + dy * dy + dz * dz);
+  }
+  const double r = block_sum_d(acc, s_red);
+  if (threadIdx.x == 0) d.partials[(uint64_t)blockIdx.x * 4] = r;
+}
+
+template <int F>
+__global__ __launch_bounds__(kThreads) void k_remove_mean(Dev d, const double* vmean) {
+  const PBlock pb = d.pblocks[blockIdx.x];
+  const BoxDev& B = d.boxes[pb.box];
+  const StatePtrs S = d.S[d.ctrl->cur];
+  const uint32_t pend = B.pbase + B.np;
+  const double V[3] = {vmean[3 * pb.box], vmean[3 * pb.box + 1], vmean[3 * pb.box + 2]};
+  for (int s = 0; s < kPartBlock / kThreads; ++s) {
+    const uint32_t i = pb.p0 + s * kThreads + threadIdx.x;
+    if (i >= pend) continue;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if constexpr (F == kFormF64) {
+        double* p = (double*)S.b[k];
+        p[i] = p[i] - V[k];
+      } else {
+        float* p = (float*)S.b[k];
+        p[i] = (float)((double)p[i] - V[k]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+#define MPC_FORM_DISPATCH(form, KERNEL, ...)                                  \
+  do {                                                                       \
+    switch (form) {                                                          \
+      case kFormF64: hipLaunchKernelGGL(KERNEL<kFormF64>, __VA_ARGS__); break; \
+      case kFormF32: hipLaunchKernelGGL(KERNEL<kFormF32>, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL(KERNEL<kFormSplit>, __VA_ARGS__); break;     \
+    }                                                                        \
+  } while (0)
+
+hipError_t launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s) {
+  uint64_t blocks = (n + kThreads - 1) / kThreads;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_zero_u32, dim3((uint32_t)blocks), dim3(kThreads), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_ctrl(const Dev& d, const Launch& l, uint64_t step, uint32_t cur,
+                           int32_t reorder, int clear_err) {
+  hipLaunchKernelGGL(k_set_ctrl, dim3(1), dim3(1), 0, l.stream, d.ctrl, step, cur, reorder,
+                     clear_err);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(const Dev& d, const Launch& l) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, l.stream, d.ctrl);
+  return hipGetLastError();
+}
+
+hipError_t launch_key_hist(const Dev& d, const Launch& l) {
+  if (l.npblocks == 0) return hipSuccess;
+  MPC_FORM_DISPATCH(l.form, k_key_hist, dim3(l.npblocks), dim3(kThreads), 0, l.stream, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const Dev& d, const Launch& l) {
+  hipLaunchKernelGGL(k_scan_reduce, dim3(l.nscan), dim3(kThreads), 0, l.stream, d.hist,
+                     d.scan_blk);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, l.stream, d.scan_blk, l.nscan);
+  hipLaunchKernelGGL(k_scan_down, dim3(l.nscan), dim3(kThreads), 0, l.stream, d.hist,
+                     d.scan_blk, d.offset, l.nscan);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const Dev& d, const Launch& l) {
+  if (l.ntot == 0) return hipSuccess;
+  const uint32_t blocks = (uint32_t)((l.ntot + kThreads * 4 - 1) / (kThreads * 4));
+  hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(kThreads), 0, l.stream, d.key, d.hist,
+                     d.offset, d.perm, (uint32_t)l.ntot, (uint32_t)l.ctot, d.ctrl);
+  return hipGetLastError();
+}
+
+hipError_t launch_collide(const Dev& d, const Launch& l) {
+  if (l.ntiles == 0) return hipSuccess;
+  MPC_FORM_DISPATCH(l.form, k_collide, dim3(l.collide_grid), dim3(kCollideThreads), 0, l.stream, d,
+                    l.ntiles, l.xcd_remap);
+  return hipGetLastError();
+}
+
+hipError_t launch_canon_perm(const Dev& d, const Launch& l) {
+  const uint64_t blocks = (l.ctot + kThreads - 1) / kThreads;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_canon_perm, dim3((uint32_t)blocks), dim3(kThreads), 0, l.stream, d.perm,
+                     d.offset, l.ctot, (uint32_t)l.ntot);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_state(const Dev& d, const Launch& l, uint64_t seed) {
+  if (l.npblocks == 0) return hipSuccess;
+  MPC_FORM_DISPATCH(l.form, k_init_state, dim3(l.npblocks), dim3(kThreads), 0, l.stream, d,
+                    (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+  return hipGetLastError();
+}
+
+hipError_t launch_obs_pass1(const Dev& d, const Launch& l) {
+  if (l.npblocks == 0) return hipSuccess;
+  MPC_FORM_DISPATCH(l.form, k_obs_pass1, dim3(l.npblocks), dim3(kThreads), 0, l.stream, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_obs_pass2(const Dev& d, const Launch& l, const double* vmean) {
+  if (l.npblocks == 0) return hipSuccess;
+  MPC_FORM_DISPATCH(l.form, k_obs_pass2, dim3(l.npblocks), dim3(kThreads), 0, l.stream, d,
+                    vmean);
+  return hipGetLastError();
+}
+
+hipError_t launch_remove_mean(const Dev& d, const Launch& l, const double* vmean) {
+  if (l.npblocks == 0) return hipSuccess;
+  MPC_FORM_DISPATCH(l.form, k_remove_mean, dim3(l.npblocks), dim3(kThreads), 0, l.stream, d,
+                    vmean);
+  return hipGetLastError();
+}
+
+}  // namespace mpc

@@ -1,0 +1,66 @@
+"""The C-ABI library loads on the CPU host and exports every declared call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpc.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(mpc_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_expected_calls():
+    names = declared_symbols()
+    for must in ["mpc_workspace_bytes", "mpc_create", "mpc_step", "mpc_observables",
+                 "mpc_set_state", "mpc_get_state", "mpc_get_binning", "mpc_destroy"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2406_15236_amd as m
+    if not os.path.exists(m.LIB):
+        pytest.skip("library not built")
+    lib = ctypes.CDLL(m.LIB)
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert sorted(m.SYMBOLS) == declared_symbols()
+
+
+def test_workspace_planning_and_validation_on_host():
+    """Parameter checks and the workspace size need no GPU."""
+    import paper_2406_15236_amd as m
+    import synth
+    if not os.path.exists(m.LIB):
+        pytest.skip("library not built")
+    c1 = synth.config("C1")
+    p = m.make_params(c1, "fp64")
+    nb = m.workspace_bytes(p)
+    n = 40960
+    assert nb >= 2 * 48 * n + 8 * n
+    # FP32 and split need less state
+    assert m.workspace_bytes(m.make_params(c1, "fp32")) < nb
+    bad = m.make_params(dict(c1, h=-0.1))
+    with pytest.raises(m.MPCError) as e:
+        m.workspace_bytes(bad)
+    assert e.value.code == m.EINVAL
+    big = m.make_params(dict(c1, L=(2048, 2048, 1024)))  # 4.3e10 particles
+    with pytest.raises(m.MPCError) as e:
+        m.workspace_bytes(big)
+    assert e.value.code == m.ERANGE
+    split_big = m.make_params(dict(c1, L=(4096, 8, 8), density=1.0), "split")
+    with pytest.raises(m.MPCError) as e:
+        m.workspace_bytes(split_big)
+    assert e.value.code == m.ERANGE
+    mixed = [m.make_params(c1, "fp64"), m.make_params(c1, "fp32")]
+    with pytest.raises(m.MPCError) as e:
+        m.workspace_bytes(mixed)
+    assert e.value.code == m.EINVAL
+    # batched: sizes add up
+    boxes = synth.batch_boxes(4, lmin=16, lmax=20)
+    tot = m.workspace_bytes([m.make_params(b) for b in boxes])
+    assert tot > max(m.workspace_bytes(m.make_params(b)) for b in boxes)

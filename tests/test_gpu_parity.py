@@ -1,0 +1,300 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Rules (one step from the same state):
+  * FP64 form: post-stream positions, cell keys, sort permutation and offsets
+    bit-identical; velocities within e <= 1e-12, where
+    e = |v_gpu - v_orc| / max(|v_orc|, sqrt(kT/m)) per particle.
+  * FP32 and split forms: binning bit-identical given the GPU's post-stream
+    positions; streaming within a few FP32 ulps of the FP64 result; collision
+    fed the GPU's post-stream state within e <= 2e-6 of the FP64 oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import synth
+
+pytestmark = pytest.mark.gpu
+
+DEG = math.pi / 180.0
+
+
+@pytest.fixture(scope="module")
+def mpc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_15236_amd as m
+    m.lib()
+    return m
+
+
+def box_of(L, mbs=False, walls=False, g=(0.0, 0.0, 0.0), seed=1, **kw):
+    b = dict(L=tuple(L), h=0.1, alpha=130.0 * DEG, kT=1.0, mass=1.0, density=10.0,
+             seed=seed, mbs=mbs, walls=walls, g=tuple(g))
+    b.update(kw)
+    return b
+
+
+def oparams(box):
+    return orc.Params(L=box["L"], h=box["h"], alpha=box["alpha"], kT=box["kT"],
+                      mass=box["mass"], density=box["density"], seed=box["seed"],
+                      mbs=box["mbs"], walls=box["walls"], g=box["g"])
+
+
+def rel_err(vg, vo, box):
+    floor = math.sqrt(box["kT"] / box["mass"])
+    return np.linalg.norm(vg - vo, axis=0) / np.maximum(np.linalg.norm(vo, axis=0), floor)
+
+
+def report(name, e):
+    print(f"{name}: max e = {e.max():.3e}, p99 = {np.quantile(e, 0.99):.3e}, n = {e.size}")
+
+
+FP64_CASES = [
+    # L, mbs, walls, gravity, R, t0
+    ((16, 16, 16), False, False, (0, 0, 0), 0, 0),      # C1 shape, in place
+    ((16, 16, 16), False, False, (0, 0, 0), 1, 7),      # sorted output
+    ((13, 9, 11), True, False, (0, 0, 0), 1, 3),        # ragged tiles, thermostat
+    ((13, 9, 11), True, False, (0, 0, 0), 3, 2),        # reorder step of R = 3
+    ((12, 10, 8), True, True, (2e-3, 0, 0), 0, 2),      # walls + phantoms + gravity
+    ((12, 10, 8), True, True, (2e-3, 0, 0), 1, 11),
+    ((7, 33, 5), False, False, (0, 0, 0), 0, 123456),   # odd shape, large step index
+]
+
+
+@pytest.mark.parametrize("L,mbs,walls,g,R,t0", FP64_CASES)
+def test_fp64_one_step(mpc, L, mbs, walls, g, R, t0):
+    box = box_of(L, mbs=mbs, walls=walls, g=g, seed=5 + t0)
+    x, v = synth.box_state(L, seed=11 + t0)
+    print(f"case L={L} mbs={mbs} walls={walls} R={R} t0={t0}", flush=True)
+    with mpc.Sim(box, form="fp64", reorder_every=R) as sim:
+        sim.set_state(x, v)
+        sim.set_step(t0)
+        sim.step(1)
+        xg, vg = sim.get_state()
+        kg, pg, og = sim.get_binning()
+        assert sim.get_step() == t0 + 1
+    sorted_out = R > 0 and (t0 + 1) % R == 0
+    xo, vo, ko, po, oo = orc.step(oparams(box), t0, x, v, reorder=sorted_out, binning=True)
+    np.testing.assert_array_equal(kg, ko)
+    np.testing.assert_array_equal(pg, po)
+    np.testing.assert_array_equal(og, oo)
+    np.testing.assert_array_equal(xg, xo)
+    e = rel_err(vg, vo, box)
+    report("fp64", e)
+    assert e.max() <= 1e-12
+
+
+def test_fp64_c1_100_steps_graph(mpc):
+    """C1: 16^3, 10 per cell, 100 steps replayed from a captured graph."""
+    box = synth.config("C1")
+    x, v = synth.box_state(box["L"], seed=1)
+    with mpc.Sim(box, form="fp64", graph=True) as sim:
+        sim.set_state(x, v)
+        o0 = sim.observables()
+        sim.step(100)
+        xg, vg = sim.get_state()
+        o1 = sim.observables()
+    p = oparams(box)
+    xo, vo = orc.run(p, x, v, 100)
+    d = np.abs(xg - xo)
+    d = np.minimum(d, 16.0 - d)
+    print(f"C1 100 steps: max |dx| = {d.max():.3e}")
+    e = rel_err(vg, vo, box)
+    report("C1 after 100 steps", e)
+    assert d.max() < 1e-10 and e.max() < 1e-10
+    assert abs(o1["E"] - o0["E"]) / o0["E"] < 1e-12
+    assert np.abs(o1["P"] - o0["P"]).max() < 1e-10 * math.sqrt(x.shape[1])
+    oo = orc.observables(p, vo)
+    assert o1["T"] == pytest.approx(oo["T"], rel=1e-12)
+
+
+@pytest.mark.parametrize("form,walls,R", [("fp32", False, 0), ("split", False, 0),
+                                          ("split", False, 1), ("fp32", True, 0),
+                                          ("split", True, 0)])
+def test_reduced_precision_one_step(mpc, form, walls, R):
+    L = (16, 12, 10)
+    box = box_of(L, mbs=True, walls=walls, g=(1e-3, 0, 0) if walls else (0, 0, 0), seed=9)
+    x, v = synth.box_state(L, seed=21)
+    t0 = 4
+    print(f"case form={form} walls={walls} R={R}", flush=True)
+    with mpc.Sim(box, form=form, reorder_every=R) as sim:
+        sim.set_state(x, v)
+        x0, v0 = sim.get_state()       # the stored (rounded) state, exactly
+        sim.set_step(t0)
+        sim.step(1)
+        x1, v1 = sim.get_state()
+        kg, pg, og = sim.get_binning()
+    p = oparams(box)
+    sorted_out = R > 0 and (t0 + 1) % R == 0
+    # streaming against the FP64 oracle from the same stored state
+    xs, vs, _ = orc.stream(p, x0, v0)
+    x1u = x1.copy()
+    v1u = v1.copy()
+    if sorted_out:  # undo the reorder to compare particle by particle
+        x1u[:, pg] = x1
+        v1u[:, pg] = v1
+    dx = np.abs(x1u - xs)
+    for k in range(2):
+        dx[k] = np.minimum(dx[k], L[k] - dx[k])
+    if not walls:
+        dx[2] = np.minimum(dx[2], L[2] - dx[2])
+    bounced = np.any(np.sign(vs) != np.sign(v0), axis=0) if walls else np.zeros(x0.shape[1], bool)
+    print(f"{form}: max stream error {dx[:, ~bounced].max():.3e} cells "
+          f"({bounced.sum()} bounced: {dx[:, bounced].max() if bounced.any() else 0:.3e})")
+    assert dx[:, ~bounced].max() < 2e-6
+    if bounced.any():
+        # FP32 absolute positions: the crossing time (z - H) / v_z inherits
+        # ulp(H) / |v_z|; the split form bounces in FP64 from the exact position.
+        assert dx[:, bounced].max() < (1e-4 if form == "fp32" else 2e-6)
+    # binning given the GPU's post-stream positions
+    ko = orc.keys(p, t0, x1u)
+    np.testing.assert_array_equal(kg, ko)
+    po, oo = orc.sort(ko, p.ncells)
+    np.testing.assert_array_equal(pg, po)
+    np.testing.assert_array_equal(og, oo)
+    # collision fed the GPU's streamed velocities (bounce-back flips v)
+    vpre = v0.copy()
+    if walls:
+        flipped = np.all(np.sign(vs) != np.sign(v0), axis=0) & np.any(v0 != 0, axis=0)
+        vpre[:, flipped] = -v0[:, flipped]
+    vo = orc.collide(p, t0, vpre, po, oo)
+    e = rel_err(v1u, vo, box)
+    report(form, e)
+    assert e.max() <= 2e-6
+
+
+def test_batched_parity(mpc):
+    """Many uneven boxes advanced together equal each box stepped alone."""
+    boxes = synth.batch_boxes(6, seed=4, lmin=6, lmax=15)
+    states = [synth.box_state(b["L"], density=b["density"], kT=b["kT"], seed=100 + i)
+              for i, b in enumerate(boxes)]
+    t0 = 3
+    with mpc.Sim(boxes, form="fp64", reorder_every=1) as sim:
+        for i, (x, v) in enumerate(states):
+            sim.set_state(x, v, box=i)
+        sim.set_step(t0)
+        sim.step(1)
+        outs = [sim.get_state(box=i) for i in range(len(boxes))]
+        bins = [sim.get_binning(box=i) for i in range(len(boxes))]
+    for i, b in enumerate(boxes):
+        x, v = states[i]
+        xo, vo, ko, po, oo = orc.step(oparams(b), t0, x, v, reorder=True, binning=True)
+        np.testing.assert_array_equal(bins[i][0], ko)
+        np.testing.assert_array_equal(bins[i][1], po)
+        np.testing.assert_array_equal(bins[i][2], oo)
+        np.testing.assert_array_equal(outs[i][0], xo)
+        e = rel_err(outs[i][1], vo, b)
+        assert e.max() <= 1e-12, (i, e.max())
+
+
+def test_graph_and_direct_launches_agree(mpc):
+    box = box_of((10, 12, 9), mbs=True, seed=3)
+    x, v = synth.box_state(box["L"], seed=2)
+    res = []
+    for graph in (True, False):
+        with mpc.Sim(box, form="fp64", reorder_every=4, graph=graph) as sim:
+            sim.set_state(x, v)
+            sim.step(9)
+            res.append(sim.get_state())
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    np.testing.assert_array_equal(res[0][1], res[1][1])
+
+
+def test_deterministic(mpc):
+    box = box_of((12, 12, 12), mbs=True, seed=8)
+    x, v = synth.box_state(box["L"], seed=4)
+    res = []
+    for _ in range(2):
+        with mpc.Sim(box, form="split", reorder_every=1) as sim:
+            sim.set_state(x, v)
+            sim.step(10)
+            res.append(sim.get_state())
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    np.testing.assert_array_equal(res[0][1], res[1][1])
+
+
+def test_observables_match_oracle(mpc):
+    box = box_of((9, 9, 9), mass=1.5, seed=2)
+    x, v = synth.box_state(box["L"], seed=6, mass=1.5)
+    v = v + 0.25
+    with mpc.Sim(box, form="fp64") as sim:
+        sim.set_state(x, v)
+        o = sim.observables()
+    oo = orc.observables(oparams(box), v)
+    np.testing.assert_allclose(o["P"], oo["P"], rtol=1e-13, atol=1e-10)
+    assert o["E"] == pytest.approx(oo["E"], rel=1e-13)
+    assert o["T"] == pytest.approx(oo["T"], rel=1e-12)
+    assert o["N"] == x.shape[1]
+
+
+def test_device_init_statistics(mpc):
+    """Device-side initial state: uniform positions, Maxwellian velocities,
+    zero total momentum."""
+    from scipy import stats
+    box = box_of((24, 20, 16), kT=1.7, seed=1)
+    with mpc.Sim(box, form="fp64") as sim:
+        sim.init_state(12345)
+        x, v = sim.get_state()
+        o = sim.observables()
+    for k, Lk in enumerate(box["L"]):
+        assert x[k].min() >= 0 and x[k].max() < Lk
+        assert stats.kstest(x[k] / Lk, "uniform").pvalue > 1e-3
+        assert stats.kstest(v[k], stats.norm(0, math.sqrt(1.7)).cdf).pvalue > 1e-3
+    assert np.abs(o["P"]).max() < 1e-9
+    assert o["T"] == pytest.approx(1.7, rel=0.02)
+
+
+def test_error_paths(mpc):
+    import torch
+    box = box_of((8, 8, 8))
+    x, v = synth.box_state(box["L"], seed=1)
+    with mpc.Sim(box) as sim:
+        with pytest.raises(mpc.MPCError) as e:
+            sim.set_state(x[:, :-1], v[:, :-1])
+        assert e.value.code == mpc.EINVAL
+        xb = x.copy()
+        xb[0, 5] = 8.0
+        with pytest.raises(mpc.MPCError) as e:
+            sim.set_state(xb, v)
+        assert e.value.code == mpc.EINVAL
+        with pytest.raises(mpc.MPCError) as e:
+            sim.get_binning()       # no step yet
+        assert e.value.code == mpc.EINVAL
+    p = mpc.make_params(box)
+    need = mpc.workspace_bytes(p)
+    ws = torch.empty(need // 2, dtype=torch.uint8, device="cuda")
+    with pytest.raises(mpc.MPCError) as e:
+        mpc.create(p, ws.data_ptr(), need // 2, 0)
+    assert e.value.code == mpc.ENOSPACE
+
+
+def test_empty_cells_and_single_particle(mpc):
+    """Very dilute box: many empty and singly occupied cells stay exact."""
+    box = box_of((10, 10, 10), density=0.3, seed=4, mbs=True)
+    x, v = synth.box_state(box["L"], density=0.3, seed=8)
+    with mpc.Sim(box, form="fp64", reorder_every=1) as sim:
+        sim.set_state(x, v)
+        sim.step(1)
+        xg, vg = sim.get_state()
+    xo, vo = orc.step(oparams(box), 0, x, v, reorder=True)
+    np.testing.assert_array_equal(xg, xo)
+    assert rel_err(vg, vo, box).max() <= 1e-12
+
+
+def test_dense_cells_split_tile_passes(mpc):
+    """Density 60: a tile holds more particles than one on-chip pass, so
+    tiles are processed in several passes."""
+    box = box_of((6, 5, 7), density=60.0, seed=6, mbs=True)
+    x, v = synth.box_state(box["L"], density=60.0, seed=9)
+    with mpc.Sim(box, form="fp64", reorder_every=1) as sim:
+        sim.set_tiling(128, 0)
+        sim.set_state(x, v)
+        sim.step(1)
+        xg, vg = sim.get_state()
+    xo, vo = orc.step(oparams(box), 0, x, v, reorder=True)
+    np.testing.assert_array_equal(xg, xo)
+    assert rel_err(vg, vo, box).max() <= 1e-12
