@@ -28,10 +28,10 @@ CELL_FIELDS = ["nfluid", "nphantom", "vx", "vy", "vz", "K", "nx", "ny", "nz",
 CELL_STRIDE = len(CELL_FIELDS)
 
 
-def build(out: str = LIB_PATH) -> str:
+def build(out: str = LIB_PATH, src: str = _SRC) -> str:
     """Compile the oracle (gcc, -O2 -ffp-contract=off: one IEEE op per written op)."""
     cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-o", out, _SRC, "-lm"]
+           "-Wall", "-Wextra", "-I", _HERE, "-o", out, src, "-lm"]
     subprocess.run(cmd, check=True)
     return out
 
@@ -82,7 +82,33 @@ def lib():
         if not os.path.exists(LIB_PATH) or (
                 os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC)):
             build()
-        L = C.CDLL(LIB_PATH)
+        _lib = load(LIB_PATH)
+    return _lib
+
+
+class use_library:
+    """Context manager: run the wrappers against another build of the oracle
+    (the mutation tests load deliberately broken copies this way)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        lib()
+        self.saved = _lib
+        _lib = load(self.path)
+        return _lib
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+
+
+def load(path: str):
+    """Open one build of the oracle and declare its C signatures."""
+    L = C.CDLL(path)
+    if True:
         P = C.POINTER(_Params)
         u32p, f64p = C.POINTER(C.c_uint32), C.POINTER(C.c_double)
         sig = {
@@ -113,8 +139,7 @@ def lib():
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
             fn.restype, fn.argtypes = res, args
-        _lib = L
-    return _lib
+        return L
 
 
 def _f64(a):

@@ -106,10 +106,16 @@ def test_stream_exact_single_rounding(orc):
             e_unwrapped = Fraction(x[k, i]) + Fraction(p.h) * Fraction(v[k, i])
             got = Fraction(x2[k, i])
             assert 0 <= x2[k, i] < L[k]
-            if 0 <= e_unwrapped < L[k]:
-                assert x2[k, i] == float(e_unwrapped)  # correctly rounded, one rounding
+            xe = float(e_unwrapped)  # one correctly rounded x + h v
+            if 0 <= xe < L[k]:
+                assert x2[k, i] == xe
             else:
-                assert abs(got - ex) <= Fraction(2.0**-52) * L[k] or abs(got - ex) >= L[k] - 1e-9
+                # one periodic image, itself correctly rounded (wrap reading)
+                img = float(Fraction(xe) + (L[k] if xe < 0 else -L[k]))
+                img = 0.0 if img == L[k] else img
+                assert x2[k, i] == img
+                d = abs(got - ex)
+                assert min(d, L[k] - d) <= Fraction(2.0**-50) * L[k]
 
 
 def test_stream_wrap_corner(orc):
@@ -415,6 +421,32 @@ def test_phantom_count_and_velocity_laws(orc):
     assert stats.chi2.sf(chi2, keep.sum() - 1) > 1e-3
     allv = np.concatenate(vel).ravel()
     assert stats.kstest(allv, stats.norm(0, math.sqrt(p.kT / p.mass)).cdf).pvalue > 1e-3
+
+
+def test_phantoms_enter_cell_sums(orc):
+    """In wall-cut cells the phantoms join the cell: v_cm and the count include
+    them (Sec. II, Boundary conditions)."""
+    L = (6, 5, 4)
+    p = orc.Params(L=L, walls=True, mbs=True, seed=19)
+    x, v = synth.box_state(L, seed=23)
+    t = 6
+    xs, vs, key, perm, off, v2, cells = _one_step_parts(orc, p, t, x, v)
+    s = orc.shift(p, t)
+    plane = L[0] * L[1]
+    checked = 0
+    for c in range(p.ncells):
+        idx = np.nonzero(key == c)[0]
+        if idx.size == 0:
+            continue
+        cz = c // plane - 1
+        fw = _fraction_in_wall(cz, s[2], L[2])
+        ph = orc.phantoms(p, t, c, fw) if fw > 1e-15 else np.zeros((0, 3))
+        assert cells[c, 1] == len(ph)
+        tot = idx.size + len(ph)
+        Vex = [math.fsum(list(vs[k, idx]) + list(ph[:, k])) / tot for k in range(3)]
+        np.testing.assert_allclose(cells[c, 2:5], Vex, rtol=0, atol=1e-14)
+        checked += len(ph) > 0
+    assert checked > 10
 
 
 # --------------------------------------------------------------------------
