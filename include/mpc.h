@@ -184,9 +184,10 @@ int mpc_get_binning(mpc_sim* s, int32_t box, uint32_t* key, uint32_t* perm, uint
  * Returns the chosen configuration in *tile_cells and *grid (may be NULL). */
 int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* grid);
 
-/* Override the collide tiling: cells per tile (1..128, 0 = automatic) and
- * persistent grid size (0 = automatic). */
-int mpc_set_tiling(mpc_sim* s, int32_t tile_cells, int32_t grid);
+/* Override the collide tiling: cells per tile (4..32, 0 = automatic),
+ * persistent grid size (0 = automatic) and the number of rows per block of the
+ * XCD-aware tile order (0 = automatic, 8). */
+int mpc_set_tiling(mpc_sim* s, int32_t tile_cells, int32_t grid, int32_t yblock);
 
 /* Release the handle (not the workspace or the stream).  Synchronises. */
 int mpc_destroy(mpc_sim* s);

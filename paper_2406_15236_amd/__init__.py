@@ -89,7 +89,7 @@ def lib():
             "mpc_get_binning": (C.c_int, [vp, C.c_int32, u32p, u32p, u32p]),
             "mpc_autotune": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int32),
                                        C.POINTER(C.c_int32)]),
-            "mpc_set_tiling": (C.c_int, [vp, C.c_int32, C.c_int32]),
+            "mpc_set_tiling": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32]),
             "mpc_destroy": (C.c_int, [vp]),
             "mpc_strerror": (C.c_char_p, [C.c_int]),
             "mpc_last_error": (C.c_char_p, [vp]),
@@ -265,8 +265,8 @@ class Sim:
         self._c(lib().mpc_get_binning(self.h, box, _u32(key), _u32(perm), _u32(off)))
         return key, perm, off
 
-    def set_tiling(self, tile_cells: int = 0, grid: int = 0):
-        self._c(lib().mpc_set_tiling(self.h, tile_cells, grid))
+    def set_tiling(self, tile_cells: int = 0, grid: int = 0, yblock: int = 0):
+        self._c(lib().mpc_set_tiling(self.h, tile_cells, grid, yblock))
 
     def autotune(self, trial_steps: int = 3):
         tc, g = C.c_int32(0), C.c_int32(0)

@@ -18,7 +18,7 @@ using namespace mpc;
 namespace {
 
 constexpr uint64_t kMaxIndex = 0x7fffffffull;  // particle and cell indices stay below 2^31
-constexpr int kMinTileCells = 16;
+constexpr int kMinTileCells = 4;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -37,7 +37,8 @@ struct Plan {
   // byte offsets in the workspace
   size_t off_S[2][7] = {};
   size_t off_key = 0, off_perm = 0, off_hist = 0, off_offset = 0, off_scan = 0, off_ctrl = 0,
-         off_boxes = 0, off_tiles = 0, off_pblocks = 0, off_partials = 0, off_vmean = 0;
+         off_boxes = 0, off_tiles = 0, off_pblocks = 0, off_partials = 0, off_vmean = 0,
+         off_draws = 0;
   size_t total = 0;
 };
 
@@ -105,7 +106,7 @@ int make_plan(const mpc_params* p, int32_t nbox, Plan& P, std::string* why) {
     P.box[b].nlz = nlz;
     P.ntot += P.box[b].n;
     P.ctot += P.box[b].ncell;
-    P.max_tiles += (P.box[b].ncell + kMinTileCells - 1) / kMinTileCells;
+    P.max_tiles += (uint64_t)q.L[1] * nlz * ((q.L[0] + kMinTileCells - 1) / kMinTileCells);
     P.npblocks += (P.box[b].n + kPartBlock - 1) / kPartBlock;
   }
   P.nscan = (uint32_t)((P.ctot + kScanBlock - 1) / kScanBlock);
@@ -140,6 +141,7 @@ int make_plan(const mpc_params* p, int32_t nbox, Plan& P, std::string* why) {
   P.off_pblocks = take(sizeof(PBlock) * P.npblocks);
   P.off_partials = take(sizeof(double) * 4 * P.npblocks);
   P.off_vmean = take(sizeof(double) * 3 * nbox);
+  P.off_draws = take(sizeof(CellDraw) * P.cpad);
   P.total = off;
   return MPC_OK;
 }
@@ -179,7 +181,7 @@ struct mpc_sim {
   bool graph_ready = false;
   hipGraphExec_t gexec = nullptr;
   hipStream_t capture_stream = nullptr;
-  int tile_override = 0, grid_override = 0;
+  int tile_override = 0, grid_override = 0, yblock = 8;
   int num_cu = 256, occupancy = 4;
   double* vmean = nullptr;
   std::string err;
@@ -207,20 +209,45 @@ int auto_tile_cells(double density) {
   return t;
 }
 
+// Tiles are runs of at most T consecutive cells inside one row (fixed y and z),
+// so a tile's particles land in the rows y +- 1, z +- 1 of the next step and
+// its next-step histogram fits a small on-chip window.  Tiles are listed so
+// that the persistent grid, which hands each XCD a contiguous part of the list,
+// keeps cells that exchange particles on one XCD at the same time: each XCD
+// gets a slab of z planes, walked in blocks of `yblock` rows with z inside a
+// block, so the rows a tile reads from are in flight together.
 void build_tiles(mpc_sim* s) {
   s->tiles.clear();
+  struct Keyed {
+    uint64_t k;
+    Tile t;
+  };
+  std::vector<Keyed> keyed;
+  const int yb = std::max(1, s->yblock);
   for (size_t b = 0; b < s->boxes.size(); ++b) {
     const BoxDev& B = s->boxes[b];
     int T = s->tile_override ? s->tile_override : auto_tile_cells(B.density);
     T = std::max(kMinTileCells, std::min(kTileMaxCells, T));
-    for (uint64_t c0 = 0; c0 < B.nc; c0 += T) {
-      Tile t;
-      t.c0 = B.cbase + (uint32_t)c0;
-      t.nc = (uint16_t)std::min<uint64_t>(T, B.nc - c0);
-      t.box = (uint16_t)b;
-      s->tiles.push_back(t);
+    const uint64_t L0 = (uint64_t)B.L[0], L1 = (uint64_t)B.L[1];
+    for (uint64_t cz = 0; cz < (uint64_t)B.nlz; ++cz) {
+      for (uint64_t cy = 0; cy < L1; ++cy) {
+        for (uint64_t cx = 0; cx < L0; cx += T) {
+          Tile t;
+          t.c0 = B.cbase + (uint32_t)((cz * L1 + cy) * L0 + cx);
+          t.nc = (uint16_t)std::min<uint64_t>(T, L0 - cx);
+          t.box = (uint16_t)b;
+          const uint64_t slab = cz * 8 / (uint64_t)B.nlz;
+          const uint64_t k =
+              ((((((uint64_t)b * 8 + slab) << 12 | (cy / yb)) << 11 | cz) << 11 | cy) << 12) |
+              (cx & 0xfff);
+          keyed.push_back({k, t});
+        }
+      }
     }
   }
+  std::stable_sort(keyed.begin(), keyed.end(),
+                   [](const Keyed& a, const Keyed& b) { return a.k < b.k; });
+  for (const Keyed& kt : keyed) s->tiles.push_back(kt.t);
   s->L.ntiles = (uint32_t)s->tiles.size();
   uint32_t g = s->grid_override ? (uint32_t)s->grid_override
                                 : (uint32_t)(s->num_cu * std::max(1, s->occupancy));
@@ -428,6 +455,7 @@ int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
   s->dev.partials = (double*)(ws + P.off_partials);
   s->dev.ntot = (uint32_t)P.ntot;
   s->vmean = (double*)(ws + P.off_vmean);
+  s->dev.draws = (CellDraw*)(ws + P.off_draws);
 
   // boxes
   uint64_t pb = 0, cb = 0;
@@ -470,6 +498,8 @@ int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
   }
 
   s->L.form = s->form;
+  s->L.walls = (p[0].flags & MPC_WALLS_Z) ? 1 : 0;
+  s->L.mbs = (p[0].flags & MPC_MBS) ? 1 : 0;
   s->L.nbox = (uint32_t)nbox;
   s->L.ntot = P.ntot;
   s->L.ctot = P.ctot;
@@ -483,7 +513,9 @@ int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
     s->num_cu = prop.multiProcessorCount;
   s->occupancy = 2;
-  if (collide_occupancy(s->form, &s->occupancy) != hipSuccess || s->occupancy < 1) s->occupancy = 1;
+  if (collide_occupancy(s->form, s->L.walls, s->L.mbs, &s->occupancy) != hipSuccess ||
+      s->occupancy < 1)
+    s->occupancy = 1;
   build_tiles(s);
 
   auto fail = [&](int code) {
@@ -521,14 +553,15 @@ int mpc_set_graph(mpc_sim* s, int32_t enable) {
   return MPC_OK;
 }
 
-int mpc_set_tiling(mpc_sim* s, int32_t tile_cells, int32_t grid) {
+int mpc_set_tiling(mpc_sim* s, int32_t tile_cells, int32_t grid, int32_t yblock) {
   if (!s) return MPC_EINVAL;
   if (tile_cells != 0 && (tile_cells < kMinTileCells || tile_cells > kTileMaxCells))
     return MPC_EINVAL;
-  if (grid < 0) return MPC_EINVAL;
+  if (grid < 0 || yblock < 0 || yblock > 4096) return MPC_EINVAL;
   HIPCHK(s, hipStreamSynchronize(s->L.stream));
   s->tile_override = tile_cells;
   s->grid_override = grid;
+  s->yblock = yblock ? yblock : 8;
   build_tiles(s);
   int rc = drop_graph(s);
   if (rc) return rc;

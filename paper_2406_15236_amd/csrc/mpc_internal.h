@@ -7,9 +7,9 @@
 namespace mpc {
 
 constexpr int kThreads = 256;               // threads per workgroup (4 wave64)
-constexpr int kCollideThreads = 256;        // collide workgroup (4 wave64)
-constexpr int kTileCap = 1024;              // particles held in LDS per tile pass
-constexpr int kTileMaxCells = 128;          // cells per collide tile
+constexpr int kCollideThreads = 64;         // collide workgroup: one wave64
+constexpr int kTileCap = 256;               // particles held in LDS per tile pass
+constexpr int kTileMaxCells = 32;           // cells per collide tile (< kCollideThreads)
 constexpr int kScanItems = 16;              // cells per thread in the scan kernels
 constexpr int kScanBlock = kThreads * kScanItems;
 constexpr int kPartBlock = kThreads * 4;    // particles per block of per-particle kernels
@@ -64,6 +64,11 @@ struct Ctrl {          // device-resident step state, read by every kernel
   uint32_t pad[3];
 };
 
+struct CellDraw {       // random draws of one cell for the current step
+  double n[3];         // rotation axis
+  double Ek;           // thermostat target energy, 0 = no scaling
+};
+
 // State buffers of one form, SoA.  F64: a[0..2]=x (double), b[0..2]=v (double);
 // F32: x, v float; Split: cell (u32), a = offsets (float), b = v (float).
 struct StatePtrs {
@@ -84,11 +89,13 @@ struct Dev {           // device pointers carved from the workspace
   Tile* tiles;
   PBlock* pblocks;
   double* partials;    // per-block observable partial sums
+  CellDraw* draws;     // per-cell draws of the current step (written by the scan)
   uint32_t ntot;       // particles over all boxes (bound of every particle index)
 };
 
 struct Launch {
   int form;
+  int walls, mbs;          // feature flags (identical for all boxes)
   uint32_t nbox;
   uint64_t ntot, ctot;     // particles, cells over all boxes
   uint32_t ntiles, npblocks, nscan;
@@ -111,6 +118,6 @@ hipError_t launch_obs_pass1(const Dev& d, const Launch& l);
 hipError_t launch_obs_pass2(const Dev& d, const Launch& l, const double* vmean_dev);
 hipError_t launch_remove_mean(const Dev& d, const Launch& l, const double* vmean_dev);
 hipError_t launch_canon_perm(const Dev& d, const Launch& l);
-hipError_t collide_occupancy(int form, int* blocks_per_cu);
+hipError_t collide_occupancy(int form, int walls, int mbs, int* blocks_per_cu);
 
 }  // namespace mpc

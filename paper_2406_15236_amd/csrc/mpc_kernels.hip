@@ -21,16 +21,42 @@
 
 namespace mpc {
 
+// Box parameters and tile/control tables are read-only while a kernel runs.
+// Reading them through the constant address space lets the compiler use
+// scalar loads that later global stores cannot clobber (otherwise every use
+// after a store becomes a per-lane reload from memory).
+#define MPC_AS4 __attribute__((address_space(4)))
+using BoxRef = const MPC_AS4 BoxDev&;
+template <typename T>
+__device__ __forceinline__ const MPC_AS4 T* as_const(const T* p) {
+  return (const MPC_AS4 T*)p;
+}
+__device__ __forceinline__ Tile load_tile(const Tile* p, uint32_t i) {
+  const MPC_AS4 Tile& r = as_const(p)[i];
+  Tile t;
+  t.c0 = r.c0;
+  t.nc = r.nc;
+  t.box = r.box;
+  return t;
+}
+__device__ __forceinline__ PBlock load_pblock(const PBlock* p, uint32_t i) {
+  const MPC_AS4 PBlock& r = as_const(p)[i];
+  PBlock b;
+  b.box = r.box;
+  b.p0 = r.p0;
+  return b;
+}
+
 // ---------------------------------------------------------------------------
 // Random draws of the method
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ Words4 draw(const BoxDev& B, uint32_t j, uint32_t id, uint64_t t,
+__device__ __forceinline__ Words4 draw(BoxRef B, uint32_t j, uint32_t id, uint64_t t,
                                        uint32_t tag) {
   return philox10(j, id, (uint32_t)t, tag, B.key_lo, B.key_hi);
 }
 
 // Lattice shift of step t: s_k = u24(w_k) - 1/2 (exact 2^-24 grid).
-__device__ __forceinline__ void shift_of(const BoxDev& B, uint64_t t, double s[3]) {
+__device__ __forceinline__ void shift_of(BoxRef B, uint64_t t, double s[3]) {
   const Words4 w = draw(B, 0, 0, t, kTagShift);
   s[0] = u24_of(w.w[0]) - 0.5;
   s[1] = u24_of(w.w[1]) - 0.5;
@@ -38,7 +64,7 @@ __device__ __forceinline__ void shift_of(const BoxDev& B, uint64_t t, double s[3
 }
 
 // Uniform random axis on the unit sphere: z = 1 - 2 u1, phi = 2 pi u2.
-__device__ __forceinline__ void axis_of(const BoxDev& B, uint64_t t, uint32_t key, double n[3]) {
+__device__ __forceinline__ void axis_of(BoxRef B, uint64_t t, uint32_t key, double n[3]) {
   const Words4 w = draw(B, 0, key, t, kTagAxis);
   const double u1 = u53_of(w.w[0], w.w[1]);
   const double u2 = u53_of(w.w[2], w.w[3]);
@@ -55,7 +81,7 @@ __device__ __forceinline__ void axis_of(const BoxDev& B, uint64_t t, uint32_t ke
 // Gamma(shape, 1) by Marsaglia-Tsang; attempt j uses THERMO draw j
 // (Box-Muller cosine branch from words 0,1; acceptance uniform from 2,3).
 // Returns false if 64 attempts were rejected.
-__device__ __forceinline__ bool gamma_of(const BoxDev& B, uint64_t t, uint32_t key, double shape,
+__device__ __forceinline__ bool gamma_of(BoxRef B, uint64_t t, uint32_t key, double shape,
                                       double* out) {
   const double d = shape - 1.0 / 3.0;
   const double c = 1.0 / sqrt(9.0 * d);
@@ -81,7 +107,7 @@ __device__ __forceinline__ bool gamma_of(const BoxDev& B, uint64_t t, uint32_t k
 
 // Phantom particles of a wall-cut cell: Poisson(<N_c> f_w) count by inversion
 // on draw 0, truncated at 127.
-__device__ __forceinline__ int phantom_count(const BoxDev& B, uint64_t t, uint32_t key, double fw) {
+__device__ __forceinline__ int phantom_count(BoxRef B, uint64_t t, uint32_t key, double fw) {
   const double lam = B.density * fw;
   const Words4 w = draw(B, 0, key, t, kTagPhantom);
   const double u = u53_of(w.w[0], w.w[1]);
@@ -103,7 +129,7 @@ struct PhantomCache {
   uint32_t j;
   Words4 w;
 };
-__device__ __forceinline__ double phantom_normal(const BoxDev& B, uint64_t t, uint32_t key,
+__device__ __forceinline__ double phantom_normal(BoxRef B, uint64_t t, uint32_t key,
                                                  uint32_t m, PhantomCache& pc) {
   const uint32_t j = 1 + m / 4;
   if (pc.j != j) {
@@ -166,11 +192,12 @@ __device__ __forceinline__ float wrap32(float x, float L) {
 }
 
 // Eq.(1) in FP64 with periodic x, y and (walls) time-reversed bounce-back in z.
-__device__ __forceinline__ void stream_f64(double (&x)[3], double (&v)[3], const BoxDev& B) {
+template <bool W>
+__device__ __forceinline__ void stream_f64(double (&x)[3], double (&v)[3], BoxRef B) {
   double xe = fma(B.h, v[0], x[0]);
   double ye = fma(B.h, v[1], x[1]);
   double ze = fma(B.h, v[2], x[2]);
-  if (B.walls) {
+  if (W) {
     const double H = B.Ld[2];
     const bool lo = ze < 0.0, hi = ze > H;
     if (lo || hi) {
@@ -193,11 +220,12 @@ __device__ __forceinline__ void stream_f64(double (&x)[3], double (&v)[3], const
   x[2] = ze;
 }
 
-__device__ __forceinline__ void stream_f32(float (&x)[3], float (&v)[3], const BoxDev& B) {
+template <bool W>
+__device__ __forceinline__ void stream_f32(float (&x)[3], float (&v)[3], BoxRef B) {
   float xe = fmaf(B.hf, v[0], x[0]);
   float ye = fmaf(B.hf, v[1], x[1]);
   float ze = fmaf(B.hf, v[2], x[2]);
-  if (B.walls) {
+  if (W) {
     const float H = B.Lf[2];
     const bool lo = ze < 0.0f, hi = ze > H;
     if (lo || hi) {
@@ -250,8 +278,9 @@ __device__ __forceinline__ void split_from_double(double xd, int& c, float& o) {
   }
 }
 
+template <bool W>
 __device__ __forceinline__ void stream_split(uint32_t& cell, float (&o)[3], float (&v)[3],
-                                             const BoxDev& B) {
+                                             BoxRef B) {
   int c[3];
   split_decode(cell, c);
   int cn[3];
@@ -268,7 +297,7 @@ __device__ __forceinline__ void stream_split(uint32_t& cell, float (&o)[3], floa
     on[k] = y;
     cn[k] = c[k] + (int)fl;
   }
-  if (B.walls) {
+  if (W) {
     const int H = B.L[2];
     const bool out = cn[2] < 0 || cn[2] > H || (cn[2] == H && on[2] > 0.0f) ||
                      !isfinite(on[2]);
@@ -311,11 +340,12 @@ __device__ __forceinline__ void stream_split(uint32_t& cell, float (&o)[3], floa
   cell = split_encode(cn);
 }
 
-// Key of shifted cell coordinates c_k = floor(x_k + s_k) (x_k given as
-// integer part ci_k plus fraction xf_k in double; exact).  Invalid -> err.
-__device__ __forceinline__ uint32_t key_of(const int (&ci)[3], const double (&xf)[3],
-                                           const double (&s)[3], const BoxDev& B, uint32_t& err) {
-  int c[3];
+// Shifted cell coordinates c_k = floor(x_k + s_k) of a position given as
+// integer part ci_k plus fraction xf_k in double (exact), with periodic wrap
+// (walls: z becomes the layer index c_z + 1 in [0, H+1]).  Invalid -> err.
+__device__ __forceinline__ bool coords_of(const int (&ci)[3], const double (&xf)[3],
+                                          const double (&s)[3], BoxRef B, int (&c)[3],
+                                          uint32_t& err) {
   bool ok = true;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -340,9 +370,20 @@ __device__ __forceinline__ uint32_t key_of(const int (&ci)[3], const double (&xf
   }
   if (!ok) {
     err |= kErrKey;
-    return 0;
+    c[0] = c[1] = c[2] = 0;
   }
+  return ok;
+}
+
+__device__ __forceinline__ uint32_t linear_key(const int (&c)[3], BoxRef B) {
   return (uint32_t)((c[2] * B.L[1] + c[1]) * B.L[0] + c[0]);
+}
+
+__device__ __forceinline__ uint32_t key_of(const int (&ci)[3], const double (&xf)[3],
+                                           const double (&s)[3], BoxRef B, uint32_t& err) {
+  int c[3];
+  coords_of(ci, xf, s, B, c, err);
+  return linear_key(c, B);
 }
 
 // Per-form particle access.  P = position type, V = velocity type,
@@ -386,12 +427,19 @@ struct Form<kFormF64> {
       ((double*)S.b[k])[j] = v.v[k];
     }
   }
-  __device__ static void stream(P& p, Vv& v, const BoxDev& B) { stream_f64(p.x, v.v, B); }
-  __device__ static uint32_t key(const P& p, const double (&s)[3], const BoxDev& B,
+  template <bool W>
+  __device__ static void stream(P& p, Vv& v, BoxRef B) { stream_f64<W>(p.x, v.v, B); }
+  __device__ static uint32_t key(const P& p, const double (&s)[3], BoxRef B,
                                  uint32_t& err) {
     const int ci[3] = {0, 0, 0};
     const double xf[3] = {p.x[0], p.x[1], p.x[2]};
     return key_of(ci, xf, s, B, err);
+  }
+  __device__ static void coords(const P& p, const double (&s)[3], BoxRef B, int (&c)[3],
+                                uint32_t& err) {
+    const int ci[3] = {0, 0, 0};
+    const double xf[3] = {p.x[0], p.x[1], p.x[2]};
+    coords_of(ci, xf, s, B, c, err);
   }
 };
 
@@ -431,12 +479,19 @@ struct Form<kFormF32> {
       ((float*)S.b[k])[j] = v.v[k];
     }
   }
-  __device__ static void stream(P& p, Vv& v, const BoxDev& B) { stream_f32(p.x, v.v, B); }
-  __device__ static uint32_t key(const P& p, const double (&s)[3], const BoxDev& B,
+  template <bool W>
+  __device__ static void stream(P& p, Vv& v, BoxRef B) { stream_f32<W>(p.x, v.v, B); }
+  __device__ static uint32_t key(const P& p, const double (&s)[3], BoxRef B,
                                  uint32_t& err) {
     const int ci[3] = {0, 0, 0};
     const double xf[3] = {(double)p.x[0], (double)p.x[1], (double)p.x[2]};
     return key_of(ci, xf, s, B, err);
+  }
+  __device__ static void coords(const P& p, const double (&s)[3], BoxRef B, int (&c)[3],
+                                uint32_t& err) {
+    const int ci[3] = {0, 0, 0};
+    const double xf[3] = {(double)p.x[0], (double)p.x[1], (double)p.x[2]};
+    coords_of(ci, xf, s, B, c, err);
   }
 };
 
@@ -481,15 +536,23 @@ struct Form<kFormSplit> {
       ((float*)S.b[k])[j] = v.v[k];
     }
   }
-  __device__ static void stream(P& p, Vv& v, const BoxDev& B) {
-    stream_split(p.cell, p.o, v.v, B);
+  template <bool W>
+  __device__ static void stream(P& p, Vv& v, BoxRef B) {
+    stream_split<W>(p.cell, p.o, v.v, B);
   }
-  __device__ static uint32_t key(const P& p, const double (&s)[3], const BoxDev& B,
+  __device__ static uint32_t key(const P& p, const double (&s)[3], BoxRef B,
                                  uint32_t& err) {
     int ci[3];
     split_decode(p.cell, ci);
     const double xf[3] = {(double)p.o[0], (double)p.o[1], (double)p.o[2]};
     return key_of(ci, xf, s, B, err);
+  }
+  __device__ static void coords(const P& p, const double (&s)[3], BoxRef B, int (&c)[3],
+                                uint32_t& err) {
+    int ci[3];
+    split_decode(p.cell, ci);
+    const double xf[3] = {(double)p.o[0], (double)p.o[1], (double)p.o[2]};
+    coords_of(ci, xf, s, B, c, err);
   }
 };
 
@@ -515,13 +578,30 @@ __global__ void k_advance(Ctrl* c) {
   c->step = t + 1;
 }
 
+// hist[c] += 1 for every active lane, one atomic per distinct key in the
+// wavefront (issued by the lowest lane carrying that key).
+__device__ __forceinline__ void wave_hist_add(uint32_t* hist, uint32_t c, bool active) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint64_t pending = __ballot(active);
+  uint64_t mine = 0;
+  while (pending) {
+    const int lead = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t lc = (uint32_t)__builtin_amdgcn_readlane((int)c, lead);
+    const uint64_t same = __ballot(active && c == lc) & pending;
+    if (active && c == lc) mine = same;
+    pending &= ~same;
+  }
+  if (active && (mine & lt_mask) == 0ull) atomicAdd(&hist[c], (uint32_t)__popcll(mine));
+}
+
 // Prologue: key and histogram of step t from the current state.
-template <int F>
+template <int F, bool W>
 __global__ __launch_bounds__(kThreads) void k_key_hist(Dev d) {
   using Fm = Form<F>;
   __shared__ double s_sh[3];
-  const PBlock pb = d.pblocks[blockIdx.x];
-  const BoxDev& B = d.boxes[pb.box];
+  const PBlock pb = load_pblock(d.pblocks, blockIdx.x);
+  BoxRef B = as_const(d.boxes)[pb.box];
   const uint64_t t = d.ctrl->step;
   const StatePtrs S = d.S[d.ctrl->cur];
   if (threadIdx.x == 0) {
@@ -538,15 +618,16 @@ __global__ __launch_bounds__(kThreads) void k_key_hist(Dev d) {
 #pragma unroll
   for (int k = 0; k < kPartBlock / kThreads; ++k) {
     const uint32_t i = pb.p0 + k * kThreads + threadIdx.x;
+    uint32_t key = 0;
     if (i < pend) {
       typename Fm::P p;
       typename Fm::Vv v;
       Fm::load(S, i, p, v);
-      Fm::stream(p, v, B);
-      const uint32_t key = B.cbase + Fm::key(p, s, B, err);
+      Fm::template stream<W>(p, v, B);
+      key = B.cbase + Fm::key(p, s, B, err);
       d.key[i] = key;
-      atomicAdd(&d.hist[key], 1u);
     }
+    wave_hist_add(d.hist, key, i < pend);
   }
   if (err) atomicOr(&d.ctrl->err, err);
 }
@@ -617,14 +698,48 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ blk, u
   }
 }
 
-// Each thread owns kScanItems consecutive cells.
-__global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t* __restrict__ hist,
-                                                        const uint32_t* __restrict__ blk,
-                                                        uint32_t* __restrict__ offset,
-                                                        uint32_t nblk) {
+// Box that owns global cell c (boxes are stored in ascending cbase).
+__device__ __forceinline__ uint32_t box_of_cell(const BoxDev* boxes, uint32_t nbox, uint32_t c) {
+  uint32_t lo = 0, hi = nbox;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (as_const(boxes)[mid].cbase <= c) {
+      lo = mid;
+    } else {
+      hi = mid;
+    }
+  }
+  return lo;
+}
+
+// Random draws of one occupied cell for step t: the rotation axis and, with
+// the thermostat, the target energy E_k = kT * Gamma(3 (n - 1) / 2), where n
+// counts phantoms too (walls).  Ek = 0 means "no scaling".
+template <bool W, bool M>
+__device__ __forceinline__ void cell_draws(BoxRef B, uint64_t t, uint32_t lkey, uint32_t nf,
+                                           double sz, CellDraw& out) {
+  uint32_t ntot = nf;
+  if (W) {
+    const int cz = (int)(lkey / (uint32_t)(B.L[0] * B.L[1])) - 1;
+    const double fw = wall_fraction(sz, cz, B.L[2]);
+    if (fw > 0.0) ntot += (uint32_t)phantom_count(B, t, lkey, fw);
+  }
+  axis_of(B, t, lkey, out.n);
+  out.Ek = 0.0;
+  if (M && ntot >= 2) {
+    double gv;
+    if (gamma_of(B, t, lkey, 1.5 * (double)(ntot - 1), &gv)) out.Ek = B.kT * gv;
+  }
+}
+
+// Each thread owns kScanItems consecutive cells: offsets, then the cell draws
+// of its occupied cells (all lanes busy: one thread per 16 cells).
+template <bool W, bool M>
+__global__ __launch_bounds__(kThreads) void k_scan_down(Dev d, uint32_t nblk, uint32_t nbox,
+                                                        uint32_t ctot) {
   __shared__ uint32_t s_w[kThreads / 64];
   const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanItems;
-  const uint4* h4 = (const uint4*)(hist + base);
+  const uint4* h4 = (const uint4*)(d.hist + base);
   uint32_t v[kScanItems];
 #pragma unroll
   for (int k = 0; k < kScanItems / 4; ++k) {
@@ -638,8 +753,8 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t* __restri
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) sum += v[k];
   uint32_t total;
-  uint32_t run = blk[blockIdx.x] + block_exclusive_scan(sum, s_w, total);
-  uint4* o4 = (uint4*)(offset + base);
+  uint32_t run = d.scan_blk[blockIdx.x] + block_exclusive_scan(sum, s_w, total);
+  uint4* o4 = (uint4*)(d.offset + base);
 #pragma unroll
   for (int k = 0; k < kScanItems / 4; ++k) {
     uint4 q;
@@ -654,7 +769,36 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t* __restri
     o4[k] = q;
   }
   if (blockIdx.x == nblk - 1 && threadIdx.x == kThreads - 1)
-    offset[(uint64_t)nblk * kScanBlock] = run;
+    d.offset[(uint64_t)nblk * kScanBlock] = run;
+
+  // per-cell draws for step t
+  if (base >= ctot) return;
+  const uint64_t t = as_const(d.ctrl)->step;
+  uint32_t b = box_of_cell(d.boxes, nbox, (uint32_t)base);
+  double sz = 0.0;
+  if (W) {
+    double sh[3];
+    shift_of(as_const(d.boxes)[b], t, sh);
+    sz = sh[2];
+  }
+#pragma unroll 1
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint32_t c = (uint32_t)base + k;
+    if (c >= ctot) break;
+    while (c >= as_const(d.boxes)[b].cbase + as_const(d.boxes)[b].nc) {
+      ++b;
+      if (W) {
+        double sh[3];
+        shift_of(as_const(d.boxes)[b], t, sh);
+        sz = sh[2];
+      }
+    }
+    if (v[k] == 0u) continue;
+    BoxRef B = as_const(d.boxes)[b];
+    CellDraw cd;
+    cell_draws<W, M>(B, t, c - B.cbase, v[k], sz, cd);
+    d.draws[c] = cd;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -666,23 +810,44 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict
                                                       const uint32_t* __restrict__ offset,
                                                       uint32_t* __restrict__ perm, uint32_t n,
                                                       uint32_t ncell, Ctrl* ctrl) {
+  // Lanes of a wavefront that carry the same key take their slots with one
+  // atomic of the run's leader (lowest lane); the others are ranked after it.
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint32_t bad = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const uint32_t i = blockIdx.x * (kThreads * 4) + k * kThreads + threadIdx.x;
-    if (i < n) {
-      const uint32_t c = key[i];
-      if (c >= ncell) {
+    uint32_t c = i < n ? key[i] : 0xffffffffu;
+    if (i < n && c >= ncell) {
+      bad = 1;
+      c = 0xffffffffu;
+    }
+    // group equal keys: find the leader (lowest lane) of each key
+    uint64_t pending = __ballot(c != 0xffffffffu);
+    uint64_t my_group = 0;
+    while (pending) {
+      const int lead = __ffsll((unsigned long long)pending) - 1;
+      const uint32_t lc = (uint32_t)__builtin_amdgcn_readlane((int)c, lead);
+      const uint64_t same = __ballot(c == lc) & pending;
+      if (c == lc && ((pending >> lane) & 1ull)) my_group = same;
+      pending &= ~same;
+    }
+    const bool valid = c != 0xffffffffu;
+    const uint32_t cnt = valid ? (uint32_t)__popcll(my_group) : 0u;
+    const uint32_t rank = valid ? (uint32_t)__popcll(my_group & lt_mask) : 0u;
+    const bool leader = valid && rank == 0;
+    uint32_t old = 0;
+    if (leader) old = atomicSub(&hist[c], cnt);
+    const int lead_lane = valid ? (__ffsll((unsigned long long)my_group) - 1) : (int)lane;
+    old = __shfl(old, lead_lane, 64);
+    if (valid) {
+      const uint32_t slot = offset[c] + old - 1u - rank;
+      if (old < cnt || slot >= n) {
         bad = 1;
-        continue;
+      } else {
+        perm[slot] = i;
       }
-      const uint32_t old = atomicSub(&hist[c], 1u);
-      const uint32_t slot = offset[c] + old - 1u;
-      if (old == 0u || slot >= n) {
-        bad = 1;
-        continue;
-      }
-      perm[slot] = i;
     }
   }
   if (bad) atomicOr(&ctrl->err, kErrKey);
@@ -691,31 +856,58 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict
 // ---------------------------------------------------------------------------
 // Collide (+ stream/bin of the next step)
 // ---------------------------------------------------------------------------
+// Number of entries of seg[b..e) smaller than i (four independent LDS reads
+// per trip so that they overlap).
+__device__ __forceinline__ uint32_t rank_in_segment(const uint32_t* seg, uint32_t b, uint32_t e,
+                                                    uint32_t i) {
+  uint32_t r = 0, q = b;
+  for (; q + 4 <= e; q += 4) {
+    const uint32_t a0 = seg[q], a1 = seg[q + 1], a2 = seg[q + 2], a3 = seg[q + 3];
+    r += (a0 < i ? 1u : 0u) + (a1 < i ? 1u : 0u) + (a2 < i ? 1u : 0u) + (a3 < i ? 1u : 0u);
+  }
+  for (; q < e; ++q) r += seg[q] < i ? 1u : 0u;
+  return r;
+}
+
 struct CellLds {
-  double V[3];
-  double n[3];
-  double kappa;
+  double V[3];   // centre-of-mass velocity
+  double R[9];   // kappa * rotation matrix, row major
   uint32_t active;
   uint32_t pad;
 };
 
+// kappa * R(alpha, n): R = cos(a) I + sin(a) [n]x + (1 - cos(a)) n n^T, so that
+// R u = cos(a) u + sin(a) n x u + (1 - cos(a)) (n . u) n  (Eq. 2).
+__device__ __forceinline__ void rotation_matrix(BoxRef B, const double (&n)[3], double kappa,
+                                                double (&R)[9]) {
+  const double ca = B.ca, sa = B.sa, omc = B.omc;
+  R[0] = kappa * (ca + omc * n[0] * n[0]);
+  R[1] = kappa * (omc * n[0] * n[1] - sa * n[2]);
+  R[2] = kappa * (omc * n[0] * n[2] + sa * n[1]);
+  R[3] = kappa * (omc * n[1] * n[0] + sa * n[2]);
+  R[4] = kappa * (ca + omc * n[1] * n[1]);
+  R[5] = kappa * (omc * n[1] * n[2] - sa * n[0]);
+  R[6] = kappa * (omc * n[2] * n[0] - sa * n[1]);
+  R[7] = kappa * (omc * n[2] * n[1] + sa * n[0]);
+  R[8] = kappa * (ca + omc * n[2] * n[2]);
+}
+
 // Sums and random draws of one cell, one thread per cell.  Velocities of the
 // cell's fluid particles are sv[k][b..e) in canonical order.
-template <int F>
-__device__ void cell_work(const BoxDev& B, uint64_t t, uint32_t lkey, double sz,
+template <int F, bool W, bool M>
+__device__ void cell_work(BoxRef B, uint64_t t, uint32_t lkey, double sz,
+                          const CellDraw* __restrict__ draws, uint32_t gkey,
                           const typename Form<F>::Vs* __restrict__ sv0,
                           const typename Form<F>::Vs* __restrict__ sv1,
                           const typename Form<F>::Vs* __restrict__ sv2, uint32_t b, uint32_t e,
                           CellLds& out) {
   const uint32_t nf = e - b;
   out.active = 0u;
-  out.kappa = 1.0;
   if (nf == 0) return;
   int nph = 0;
-  double fw = 0.0;
-  if (B.walls) {
+  if (W) {
     const int cz = (int)(lkey / (uint32_t)(B.L[0] * B.L[1])) - 1;
-    fw = wall_fraction(sz, cz, B.L[2]);
+    const double fw = wall_fraction(sz, cz, B.L[2]);
     if (fw > 0.0) nph = phantom_count(B, t, lkey, fw);
   }
   const uint32_t ntot = nf + (uint32_t)nph;
@@ -734,13 +926,13 @@ __device__ void cell_work(const BoxDev& B, uint64_t t, uint32_t lkey, double sz,
       }
       s[k] = tt;
     };
-#pragma unroll 1
+#pragma unroll 4
     for (uint32_t q = b; q < e; ++q) {
       add(0, mf * sv0[q]);
       add(1, mf * sv1[q]);
       add(2, mf * sv2[q]);
     }
-    if (nph) {
+    if (W && nph) {
       PhantomCache pc;
       pc.j = 0xffffffffu;
 #pragma unroll 1
@@ -754,13 +946,13 @@ __device__ void cell_work(const BoxDev& B, uint64_t t, uint32_t lkey, double sz,
     for (int k = 0; k < 3; ++k) V[k] = (double)((s[k] + c[k]) / Mf);
   } else {
     double P[3] = {0.0, 0.0, 0.0};
-#pragma unroll 1
+#pragma unroll 4
     for (uint32_t q = b; q < e; ++q) {
       P[0] = P[0] + m * (double)sv0[q];
       P[1] = P[1] + m * (double)sv1[q];
       P[2] = P[2] + m * (double)sv2[q];
     }
-    if (nph) {
+    if (W && nph) {
       PhantomCache pc;
       pc.j = 0xffffffffu;
 #pragma unroll 1
@@ -769,26 +961,28 @@ __device__ void cell_work(const BoxDev& B, uint64_t t, uint32_t lkey, double sz,
         for (int k = 0; k < 3; ++k)
           P[k] = P[k] + m * (B.sd * phantom_normal(B, t, lkey, 3 * q + k, pc));
     }
-    const double M = (double)ntot * m;
-    V[0] = P[0] / M;
-    V[1] = P[1] / M;
-    V[2] = P[2] / M;
+    const double Mtot = (double)ntot * m;
+    V[0] = P[0] / Mtot;
+    V[1] = P[1] / Mtot;
+    V[2] = P[2] / Mtot;
   }
   out.V[0] = V[0];
   out.V[1] = V[1];
   out.V[2] = V[2];
   if (ntot < 2) return;
   out.active = 1u;
-  axis_of(B, t, lkey, out.n);
-  if (B.mbs) {
+  const CellDraw cd = draws[gkey];
+  const double n[3] = {cd.n[0], cd.n[1], cd.n[2]};
+  double kappa = 1.0;
+  if (M && cd.Ek > 0.0) {
     double K = 0.0;
-#pragma unroll 1
+#pragma unroll 4
     for (uint32_t q = b; q < e; ++q) {
       const double dx = (double)sv0[q] - V[0], dy = (double)sv1[q] - V[1],
                    dz = (double)sv2[q] - V[2];
       K = K + m * (dx * dx + dy * dy + dz * dz);
     }
-    if (nph) {
+    if (W && nph) {
       PhantomCache pc;
       pc.j = 0xffffffffu;
 #pragma unroll 1
@@ -803,25 +997,20 @@ __device__ void cell_work(const BoxDev& B, uint64_t t, uint32_t lkey, double sz,
         K = K + m * (d2[0] * d2[0] + d2[1] * d2[1] + d2[2] * d2[2]);
       }
     }
-    if (K > 0.0) {
-      double gv;
-      if (gamma_of(B, t, lkey, 1.5 * (double)(ntot - 1), &gv)) {
-        const double Ek = B.kT * gv;
-        out.kappa = sqrt((2.0 * Ek) / K);
-      }
-    }
+    if (K > 0.0) kappa = sqrt((2.0 * cd.Ek) / K);
   }
+  rotation_matrix(B, n, kappa, out.R);
 }
 
-template <int F>
-__global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu(2)))
+template <int F, bool W, bool M>
+__global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu(W ? 2 : 3)))
 void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   using Fm = Form<F>;
   using Vs = typename Fm::Vs;
   using Xs = typename Fm::Xs;
   constexpr int NT = kCollideThreads;
   constexpr int NS = kTileCap / kCollideThreads;
-  static_assert(kTileMaxCells <= NT, "one thread per cell of a tile");
+  static_assert(kTileMaxCells < NT, "one thread per cell offset (nc + 1) of a tile");
   __shared__ uint32_t s_off[kTileMaxCells + 1];
   __shared__ uint32_t s_idx[kTileCap];   // perm entries, segment order as scattered
   __shared__ uint32_t s_idxc[kTileCap];  // storage index at the canonical position
@@ -831,10 +1020,13 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   __shared__ uint32_t s_c[Fm::kHasCell ? kTileCap : 1];
   __shared__ CellLds s_cell[kTileMaxCells];
   __shared__ double s_sh[6];
+  // next-step histogram of the tile: cells x0-1 .. x0+nc of rows (y0+-1, z0+-1)
+  constexpr int kWin = 9 * (kTileMaxCells + 2);
+  __shared__ uint32_t s_hw[kWin];
 
-  const uint64_t t = d.ctrl->step;
-  const uint32_t cur = d.ctrl->cur;
-  const int32_t R = d.ctrl->reorder;
+  const uint64_t t = as_const(d.ctrl)->step;
+  const uint32_t cur = as_const(d.ctrl)->cur;
+  const int32_t R = as_const(d.ctrl)->reorder;
   const bool sorted = R > 0 && (t + 1) % (uint64_t)R == 0;
   const StatePtrs in = d.S[cur];
   const StatePtrs out = sorted ? d.S[cur ^ 1u] : d.S[cur];
@@ -852,6 +1044,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
     stride = G / 8;
   }
   uint32_t cached_box = 0xffffffffu;
+  uint32_t pf_tile = 0xffffffffu, pf_off = 0;  // prefetched offsets of the next tile
 
   for (uint32_t it = first;; it += stride) {
     uint32_t tile;
@@ -863,10 +1056,11 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
       if (it >= ntiles) break;
       tile = it;
     }
-    const Tile T = d.tiles[tile];
-    const BoxDev& B = d.boxes[T.box];
+    const Tile T = load_tile(d.tiles, tile);
+    BoxRef B = as_const(d.boxes)[T.box];
     __syncthreads();  // LDS of the previous tile is free
-    if (threadIdx.x <= T.nc) s_off[threadIdx.x] = d.offset[T.c0 + threadIdx.x];
+    if (threadIdx.x <= T.nc)
+      s_off[threadIdx.x] = pf_tile == tile ? pf_off : d.offset[T.c0 + threadIdx.x];
     if (threadIdx.x == 0 && T.box != cached_box) {
       double s0[3], s1[3];
       shift_of(B, t, s0);
@@ -879,8 +1073,14 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
       s_sh[5] = s1[2];
     }
     cached_box = T.box;
-    __syncthreads();
     const uint32_t lkey0 = T.c0 - B.cbase;
+    // tiles lie inside one row: (x0 .. x0 + nc - 1, y0, z0)
+    const int x0 = (int)(lkey0 % (uint32_t)B.L[0]);
+    const int y0 = (int)((lkey0 / (uint32_t)B.L[0]) % (uint32_t)B.L[1]);
+    const int z0 = (int)(lkey0 / (uint32_t)(B.L[0] * B.L[1]));
+    const int WX = (int)T.nc + 2;
+    for (int i = threadIdx.x; i < 9 * WX; i += NT) s_hw[i] = 0u;
+    __syncthreads();
 
     uint32_t cs = 0;
     while (cs < T.nc) {
@@ -911,19 +1111,23 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
         // one cell beyond capacity: stream and re-bin its particles unchanged
         err |= kErrCellOverflow;
         const double snx[3] = {s_sh[3], s_sh[4], s_sh[5]};
-        for (uint32_t q = threadIdx.x; q < np; q += NT) {
-          const uint32_t i = d.perm[base + q];
-          if (i >= d.ntot) continue;
-          typename Fm::P p;
-          typename Fm::Vv v;
-          Fm::load(in, i, p, v);
-          Fm::stream(p, v, B);
-          const uint32_t j = sorted ? base + q : i;
-          Fm::store(out, j, p, v);
-          Fm::stream(p, v, B);
-          const uint32_t kn = B.cbase + Fm::key(p, snx, B, err);
-          d.key[j] = kn;
-          atomicAdd(&d.hist[kn], 1u);
+        for (uint32_t q0 = 0; q0 < np; q0 += NT) {
+          const uint32_t q = q0 + threadIdx.x;
+          const uint32_t i = q < np ? d.perm[base + q] : d.ntot;
+          const bool live = i < d.ntot;
+          uint32_t kn = 0;
+          if (live) {
+            typename Fm::P p;
+            typename Fm::Vv v;
+            Fm::load(in, i, p, v);
+            Fm::template stream<W>(p, v, B);
+            const uint32_t j = sorted ? base + q : i;
+            Fm::store(out, j, p, v);
+            Fm::template stream<W>(p, v, B);
+            kn = B.cbase + Fm::key(p, snx, B, err);
+            d.key[j] = kn;
+          }
+          wave_hist_add(d.hist, kn, live);
         }
         cs = ce;
         __syncthreads();
@@ -967,10 +1171,8 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             const uint32_t i = ii[k];
             const uint32_t c = cs + s_lc[q];
             const uint32_t b = s_off[c] - base, e = s_off[c + 1] - base;
-            uint32_t r = 0;
-            for (uint32_t q2 = b; q2 < e; ++q2) r += s_idx[q2] < i ? 1u : 0u;
-            const uint32_t qc = b + r;
-            Fm::stream(p[k], v[k], B);
+            const uint32_t qc = b + rank_in_segment(s_idx, b, e, i);
+            Fm::template stream<W>(p[k], v[k], B);
             Fm::to_lds(p[k], s_x[0], s_x[1], s_x[2], s_c, qc);
             s_v[0][qc] = v[k].v[0];
             s_v[1][qc] = v[k].v[1];
@@ -981,11 +1183,27 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
       }
       __syncthreads();
 
-      // Phase C: one thread per cell
+      // Phase C: one thread per cell (first pass of a tile also prefetches the
+      // next tile's offsets)
+      if (cs == 0) {
+        const uint32_t itn = it + stride;
+        uint32_t tn = 0xffffffffu;
+        if (per_xcd) {
+          if (itn < per_xcd && xcd * per_xcd + itn < ntiles) tn = xcd * per_xcd + itn;
+        } else if (itn < ntiles) {
+          tn = itn;
+        }
+        pf_tile = tn;
+        if (tn != 0xffffffffu) {
+          const Tile Tn = load_tile(d.tiles, tn);
+          if (threadIdx.x <= Tn.nc) pf_off = d.offset[Tn.c0 + threadIdx.x];
+        }
+      }
       if (cs + threadIdx.x < ce) {
         const uint32_t c = cs + threadIdx.x;
         const uint32_t b = s_off[c] - base, e = s_off[c + 1] - base;
-        cell_work<F>(B, t, lkey0 + c, s_sh[2], s_v[0], s_v[1], s_v[2], b, e, s_cell[c - cs]);
+        cell_work<F, W, M>(B, t, lkey0 + c, s_sh[2], d.draws, T.c0 + c, s_v[0], s_v[1], s_v[2], b, e,
+                           s_cell[c - cs]);
       }
       __syncthreads();
 
@@ -995,6 +1213,8 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
       for (int k = 0; k < NS; ++k) {
         const uint32_t q = threadIdx.x + k * NT;
         __builtin_amdgcn_sched_barrier(0);
+        uint32_t kn = 0;
+        bool live = false;
         if (q < np) {
           typename Fm::P p;
           typename Fm::Vv v;
@@ -1006,17 +1226,13 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
           if constexpr (F == kFormSplit) {
             if (C.active) {
               const float V[3] = {(float)C.V[0], (float)C.V[1], (float)C.V[2]};
-              const float n[3] = {(float)C.n[0], (float)C.n[1], (float)C.n[2]};
-              const float ca = (float)B.ca, sa = (float)B.sa, omc = (float)B.omc;
-              const float kap = (float)C.kappa;
               const float u[3] = {v.v[0] - V[0], v.v[1] - V[1], v.v[2] - V[2]};
-              const float ndu = n[0] * u[0] + n[1] * u[1] + n[2] * u[2];
-              const float cr[3] = {n[1] * u[2] - n[2] * u[1], n[2] * u[0] - n[0] * u[2],
-                                   n[0] * u[1] - n[1] * u[0]};
-              const float f = omc * ndu;
 #pragma unroll
-              for (int a = 0; a < 3; ++a)
-                v.v[a] = V[a] + kap * (ca * u[a] + sa * cr[a] + f * n[a]);
+              for (int a = 0; a < 3; ++a) {
+                const float r0 = (float)C.R[3 * a], r1 = (float)C.R[3 * a + 1],
+                            r2 = (float)C.R[3 * a + 2];
+                v.v[a] = V[a] + fmaf(r0, u[0], fmaf(r1, u[1], r2 * u[2]));
+              }
             }
             if (B.grav) {
 #pragma unroll
@@ -1026,16 +1242,9 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             double w[3] = {(double)v.v[0], (double)v.v[1], (double)v.v[2]};
             if (C.active) {
               const double u[3] = {w[0] - C.V[0], w[1] - C.V[1], w[2] - C.V[2]};
-              const double ndu = C.n[0] * u[0] + C.n[1] * u[1] + C.n[2] * u[2];
-              const double cr[3] = {C.n[1] * u[2] - C.n[2] * u[1],
-                                    C.n[2] * u[0] - C.n[0] * u[2],
-                                    C.n[0] * u[1] - C.n[1] * u[0]};
-              const double f = B.omc * ndu;
 #pragma unroll
-              for (int a = 0; a < 3; ++a) {
-                const double up = B.ca * u[a] + B.sa * cr[a] + f * C.n[a];
-                w[a] = C.V[a] + C.kappa * up;
-              }
+              for (int a = 0; a < 3; ++a)
+                w[a] = C.V[a] + fma(C.R[3 * a], u[0], fma(C.R[3 * a + 1], u[1], C.R[3 * a + 2] * u[2]));
             }
             if (B.grav) {
 #pragma unroll
@@ -1045,35 +1254,98 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             for (int a = 0; a < 3; ++a) v.v[a] = (Vs)w[a];
           }
           const uint32_t j = sorted ? base + q : s_idxc[q];
-          if (j >= d.ntot) {
+          if (j < d.ntot) {
+            Fm::store(out, j, p, v);
+            Fm::template stream<W>(p, v, B);
+            int c[3];
+            Fm::coords(p, snext, B, c, err);
+            kn = B.cbase + linear_key(c, B);
+            d.key[j] = kn;
+            int dx = c[0] - x0 + 1;
+            if (dx < 0) {
+              dx += B.L[0];
+            } else if (dx >= B.L[0]) {
+              dx -= B.L[0];
+            }
+            int dy = c[1] - y0;
+            if (dy > 1) {
+              dy -= B.L[1];
+            } else if (dy < -1) {
+              dy += B.L[1];
+            }
+            int dz = c[2] - z0;
+            if (!W) {
+              if (dz > 1) {
+                dz -= B.L[2];
+              } else if (dz < -1) {
+                dz += B.L[2];
+              }
+            }
+            if (dx < WX && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) {
+              atomicAdd(&s_hw[((dz + 1) * 3 + (dy + 1)) * WX + dx], 1u);
+            } else {
+              atomicAdd(&d.hist[kn], 1u);
+            }
+          } else {
             err |= kErrKey;
-            continue;
           }
-          Fm::store(out, j, p, v);
-          Fm::stream(p, v, B);
-          const uint32_t kn = B.cbase + Fm::key(p, snext, B, err);
-          d.key[j] = kn;
-          atomicAdd(&d.hist[kn], 1u);
         }
+        (void)live;
+        (void)kn;
       }
       cs = ce;
       __syncthreads();
+    }
+    // flush the tile's window into the global histogram
+    for (int i = threadIdx.x; i < 9 * WX; i += NT) {
+      const uint32_t cnt = s_hw[i];
+      if (cnt) {
+        const int dzi = i / (3 * WX), dyi = (i / WX) % 3, dx = i % WX;
+        int c[3] = {x0 - 1 + dx, y0 + dyi - 1, z0 + dzi - 1};
+        if (c[0] < 0) {
+          c[0] += B.L[0];
+        } else if (c[0] >= B.L[0]) {
+          c[0] -= B.L[0];
+        }
+        if (c[1] < 0) {
+          c[1] += B.L[1];
+        } else if (c[1] >= B.L[1]) {
+          c[1] -= B.L[1];
+        }
+        if (!W) {
+          if (c[2] < 0) {
+            c[2] += B.L[2];
+          } else if (c[2] >= B.L[2]) {
+            c[2] -= B.L[2];
+          }
+        }
+        atomicAdd(&d.hist[B.cbase + linear_key(c, B)], cnt);
+      }
     }
   }
   if (err) atomicOr(&d.ctrl->err, err);
 }
 
-hipError_t collide_occupancy(int form, int* blocks_per_cu) {
-  switch (form) {
-    case kFormF64:
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_collide<kFormF64>,
-                                                          kCollideThreads, 0);
-    case kFormF32:
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_collide<kFormF32>,
-                                                          kCollideThreads, 0);
-    default:
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_collide<kFormSplit>,
-                                                          kCollideThreads, 0);
+template <int F, bool W, bool M>
+static hipError_t occ_of(int* n) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_collide<F, W, M>, kCollideThreads, 0);
+}
+
+hipError_t collide_occupancy(int form, int walls, int mbs, int* blocks_per_cu) {
+  const int sel = form * 4 + (walls ? 2 : 0) + (mbs ? 1 : 0);
+  switch (sel) {
+    case 0: return occ_of<kFormF64, false, false>(blocks_per_cu);
+    case 1: return occ_of<kFormF64, false, true>(blocks_per_cu);
+    case 2: return occ_of<kFormF64, true, false>(blocks_per_cu);
+    case 3: return occ_of<kFormF64, true, true>(blocks_per_cu);
+    case 4: return occ_of<kFormF32, false, false>(blocks_per_cu);
+    case 5: return occ_of<kFormF32, false, true>(blocks_per_cu);
+    case 6: return occ_of<kFormF32, true, false>(blocks_per_cu);
+    case 7: return occ_of<kFormF32, true, true>(blocks_per_cu);
+    case 8: return occ_of<kFormSplit, false, false>(blocks_per_cu);
+    case 9: return occ_of<kFormSplit, false, true>(blocks_per_cu);
+    case 10: return occ_of<kFormSplit, true, false>(blocks_per_cu);
+    default: return occ_of<kFormSplit, true, true>(blocks_per_cu);
   }
 }
 
@@ -1103,8 +1375,8 @@ __global__ void k_canon_perm(uint32_t* __restrict__ perm, const uint32_t* __rest
 // ---------------------------------------------------------------------------
 template <int F>
 __global__ __launch_bounds__(kThreads) void k_init_state(Dev d, uint32_t k0, uint32_t k1) {
-  const PBlock pb = d.pblocks[blockIdx.x];
-  const BoxDev& B = d.boxes[pb.box];
+  const PBlock pb = load_pblock(d.pblocks, blockIdx.x);
+  BoxRef B = as_const(d.boxes)[pb.box];
   const StatePtrs S = d.S[d.ctrl->cur];
   const uint32_t pend = B.pbase + B.np;
   for (int s = 0; s < kPartBlock / kThreads; ++s) {
@@ -1187,8 +1459,8 @@ __device__ __forceinline__ double block_sum_d(double x, double* s_red) {
 template <int F>
 __global__ __launch_bounds__(kThreads) void k_obs_pass1(Dev d) {
   __shared__ double s_red[kThreads];
-  const PBlock pb = d.pblocks[blockIdx.x];
-  const BoxDev& B = d.boxes[pb.box];
+  const PBlock pb = load_pblock(d.pblocks, blockIdx.x);
+  BoxRef B = as_const(d.boxes)[pb.box];
   const StatePtrs S = d.S[d.ctrl->cur];
   const uint32_t pend = B.pbase + B.np;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1211,8 +1483,8 @@ __global__ __launch_bounds__(kThreads) void k_obs_pass1(Dev d) {
 template <int F>
 __global__ __launch_bounds__(kThreads) void k_obs_pass2(Dev d, const double* vmean) {
   __shared__ double s_red[kThreads];
-  const PBlock pb = d.pblocks[blockIdx.x];
-  const BoxDev& B = d.boxes[pb.box];
+  const PBlock pb = load_pblock(d.pblocks, blockIdx.x);
+  BoxRef B = as_const(d.boxes)[pb.box];
   const StatePtrs S = d.S[d.ctrl->cur];
   const uint32_t pend = B.pbase + B.np;
   const double V[3] = {vmean[3 * pb.box], vmean[3 * pb.box + 1], vmean[3 * pb.box + 2]};
@@ -1231,8 +1503,8 @@ __global__ __launch_bounds__(kThreads) void k_obs_pass2(Dev d, const double* vme
 
 template <int F>
 __global__ __launch_bounds__(kThreads) void k_remove_mean(Dev d, const double* vmean) {
-  const PBlock pb = d.pblocks[blockIdx.x];
-  const BoxDev& B = d.boxes[pb.box];
+  const PBlock pb = load_pblock(d.pblocks, blockIdx.x);
+  BoxRef B = as_const(d.boxes)[pb.box];
   const StatePtrs S = d.S[d.ctrl->cur];
   const uint32_t pend = B.pbase + B.np;
   const double V[3] = {vmean[3 * pb.box], vmean[3 * pb.box + 1], vmean[3 * pb.box + 2]};
@@ -1286,7 +1558,15 @@ hipError_t launch_advance(const Dev& d, const Launch& l) {
 
 hipError_t launch_key_hist(const Dev& d, const Launch& l) {
   if (l.npblocks == 0) return hipSuccess;
-  MPC_FORM_DISPATCH(l.form, k_key_hist, dim3(l.npblocks), dim3(kThreads), 0, l.stream, d);
+  const dim3 g(l.npblocks), b(kThreads);
+  switch (l.form * 2 + (l.walls ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((k_key_hist<kFormF64, false>), g, b, 0, l.stream, d); break;
+    case 1: hipLaunchKernelGGL((k_key_hist<kFormF64, true>), g, b, 0, l.stream, d); break;
+    case 2: hipLaunchKernelGGL((k_key_hist<kFormF32, false>), g, b, 0, l.stream, d); break;
+    case 3: hipLaunchKernelGGL((k_key_hist<kFormF32, true>), g, b, 0, l.stream, d); break;
+    case 4: hipLaunchKernelGGL((k_key_hist<kFormSplit, false>), g, b, 0, l.stream, d); break;
+    default: hipLaunchKernelGGL((k_key_hist<kFormSplit, true>), g, b, 0, l.stream, d); break;
+  }
   return hipGetLastError();
 }
 
@@ -1294,8 +1574,14 @@ hipError_t launch_scan(const Dev& d, const Launch& l) {
   hipLaunchKernelGGL(k_scan_reduce, dim3(l.nscan), dim3(kThreads), 0, l.stream, d.hist,
                      d.scan_blk);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, l.stream, d.scan_blk, l.nscan);
-  hipLaunchKernelGGL(k_scan_down, dim3(l.nscan), dim3(kThreads), 0, l.stream, d.hist,
-                     d.scan_blk, d.offset, l.nscan);
+  const dim3 g(l.nscan), b(kThreads);
+  const uint32_t nb = l.nscan, nx = l.nbox, ct = (uint32_t)l.ctot;
+  switch ((l.walls ? 2 : 0) + (l.mbs ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((k_scan_down<false, false>), g, b, 0, l.stream, d, nb, nx, ct); break;
+    case 1: hipLaunchKernelGGL((k_scan_down<false, true>), g, b, 0, l.stream, d, nb, nx, ct); break;
+    case 2: hipLaunchKernelGGL((k_scan_down<true, false>), g, b, 0, l.stream, d, nb, nx, ct); break;
+    default: hipLaunchKernelGGL((k_scan_down<true, true>), g, b, 0, l.stream, d, nb, nx, ct); break;
+  }
   return hipGetLastError();
 }
 
@@ -1309,8 +1595,27 @@ hipError_t launch_scatter(const Dev& d, const Launch& l) {
 
 hipError_t launch_collide(const Dev& d, const Launch& l) {
   if (l.ntiles == 0) return hipSuccess;
-  MPC_FORM_DISPATCH(l.form, k_collide, dim3(l.collide_grid), dim3(kCollideThreads), 0, l.stream, d,
-                    l.ntiles, l.xcd_remap);
+  const dim3 g(l.collide_grid), b(kCollideThreads);
+  const uint32_t nt = l.ntiles;
+  const int xr = l.xcd_remap;
+  switch (l.form * 4 + (l.walls ? 2 : 0) + (l.mbs ? 1 : 0)) {
+#define MPC_COLLIDE_CASE(n, F, W, M) \
+  case n: hipLaunchKernelGGL((k_collide<F, W, M>), g, b, 0, l.stream, d, nt, xr); break;
+    MPC_COLLIDE_CASE(0, kFormF64, false, false)
+    MPC_COLLIDE_CASE(1, kFormF64, false, true)
+    MPC_COLLIDE_CASE(2, kFormF64, true, false)
+    MPC_COLLIDE_CASE(3, kFormF64, true, true)
+    MPC_COLLIDE_CASE(4, kFormF32, false, false)
+    MPC_COLLIDE_CASE(5, kFormF32, false, true)
+    MPC_COLLIDE_CASE(6, kFormF32, true, false)
+    MPC_COLLIDE_CASE(7, kFormF32, true, true)
+    MPC_COLLIDE_CASE(8, kFormSplit, false, false)
+    MPC_COLLIDE_CASE(9, kFormSplit, false, true)
+    MPC_COLLIDE_CASE(10, kFormSplit, true, false)
+    MPC_COLLIDE_CASE(11, kFormSplit, true, true)
+#undef MPC_COLLIDE_CASE
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

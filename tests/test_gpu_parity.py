@@ -291,7 +291,7 @@ def test_dense_cells_split_tile_passes(mpc):
     box = box_of((6, 5, 7), density=60.0, seed=6, mbs=True)
     x, v = synth.box_state(box["L"], density=60.0, seed=9)
     with mpc.Sim(box, form="fp64", reorder_every=1) as sim:
-        sim.set_tiling(128, 0)
+        sim.set_tiling(32, 0, 0)
         sim.set_state(x, v)
         sim.step(1)
         xg, vg = sim.get_state()
