@@ -189,6 +189,11 @@ int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* 
  * XCD-aware tile order (0 = automatic, 8). */
 int mpc_set_tiling(mpc_sim* s, int32_t tile_cells, int32_t grid, int32_t yblock);
 
+/* Current collide tiling: tile_cells (0 = automatic per box), persistent grid
+ * size, rows per block of the tile order, and the number of tiles. */
+int mpc_get_tiling(mpc_sim* s, int32_t* tile_cells, int32_t* grid, int32_t* yblock,
+                   int64_t* ntiles);
+
 /* Release the handle (not the workspace or the stream).  Synchronises. */
 int mpc_destroy(mpc_sim* s);
 

@@ -55,7 +55,8 @@ class KernelTimes(C.Structure):
 SYMBOLS = ["mpc_workspace_bytes", "mpc_create", "mpc_init_state", "mpc_step",
            "mpc_step_profiled", "mpc_set_graph", "mpc_sync", "mpc_observables",
            "mpc_box_info", "mpc_get_step", "mpc_set_step", "mpc_set_state", "mpc_get_state",
-           "mpc_get_binning", "mpc_autotune", "mpc_set_tiling", "mpc_destroy", "mpc_strerror",
+           "mpc_get_binning", "mpc_autotune", "mpc_set_tiling", "mpc_get_tiling", "mpc_destroy",
+           "mpc_strerror",
            "mpc_last_error"]
 
 _lib = None
@@ -90,6 +91,8 @@ def lib():
             "mpc_autotune": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int32),
                                        C.POINTER(C.c_int32)]),
             "mpc_set_tiling": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32]),
+            "mpc_get_tiling": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
             "mpc_destroy": (C.c_int, [vp]),
             "mpc_strerror": (C.c_char_p, [C.c_int]),
             "mpc_last_error": (C.c_char_p, [vp]),
@@ -267,6 +270,11 @@ class Sim:
 
     def set_tiling(self, tile_cells: int = 0, grid: int = 0, yblock: int = 0):
         self._c(lib().mpc_set_tiling(self.h, tile_cells, grid, yblock))
+
+    def get_tiling(self) -> dict:
+        tc, g, yb, nt = C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_int64(0)
+        self._c(lib().mpc_get_tiling(self.h, C.byref(tc), C.byref(g), C.byref(yb), C.byref(nt)))
+        return {"tile_cells": tc.value, "grid": g.value, "yblock": yb.value, "ntiles": nt.value}
 
     def autotune(self, trial_steps: int = 3):
         tc, g = C.c_int32(0), C.c_int32(0)

@@ -568,6 +568,16 @@ int mpc_set_tiling(mpc_sim* s, int32_t tile_cells, int32_t grid, int32_t yblock)
   return upload_tables(s);
 }
 
+int mpc_get_tiling(mpc_sim* s, int32_t* tile_cells, int32_t* grid, int32_t* yblock,
+                   int64_t* ntiles) {
+  if (!s) return MPC_EINVAL;
+  if (tile_cells) *tile_cells = s->tile_override;
+  if (grid) *grid = (int32_t)s->L.collide_grid;
+  if (yblock) *yblock = s->yblock;
+  if (ntiles) *ntiles = (int64_t)s->L.ntiles;
+  return MPC_OK;
+}
+
 int mpc_step(mpc_sim* s, int64_t nsteps) {
   if (!s || nsteps < 0) return MPC_EINVAL;
   if (nsteps == 0) return MPC_OK;

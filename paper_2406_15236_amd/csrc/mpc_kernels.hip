@@ -157,37 +157,35 @@ __device__ __forceinline__ double wall_fraction(double sz, int cz, int H) {
 // ---------------------------------------------------------------------------
 // Storage forms
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wrap64(double x, double L) {
-  if (x < 0.0) {
-    x = x + L;
-  } else if (x >= L) {
-    x = x - L;
-  }
-  if (!(x >= 0.0 && x < L)) {
-    if (x == L) {
-      x = 0.0;
-    } else if (isfinite(x)) {
-      x = x - L * floor(x / L);
-      if (x >= L || x < 0.0) x = 0.0;
-    }
+// Periodic wrap into [0, L): one image shift (selects), then the rare cases
+// (rounding onto L, far outside, non-finite) on a cold path.
+__device__ __noinline__ double wrap64_rare(double x, double L) {
+  if (x == L) return 0.0;
+  if (isfinite(x)) {
+    x = x - L * floor(x / L);
+    if (x >= L || x < 0.0) x = 0.0;
   }
   return x;
 }
+__device__ __forceinline__ double wrap64(double x, double L) {
+  const double lo = x + L, hi = x - L;
+  x = x < 0.0 ? lo : (x >= L ? hi : x);
+  if (__builtin_expect(!(x >= 0.0 && x < L), 0)) x = wrap64_rare(x, L);
+  return x;
+}
 
+__device__ __noinline__ float wrap32_rare(float x, float L) {
+  if (x == L) return 0.0f;
+  if (isfinite(x)) {
+    x = x - L * floorf(x / L);
+    if (x >= L || x < 0.0f) x = 0.0f;
+  }
+  return x;
+}
 __device__ __forceinline__ float wrap32(float x, float L) {
-  if (x < 0.0f) {
-    x = x + L;
-  } else if (x >= L) {
-    x = x - L;
-  }
-  if (!(x >= 0.0f && x < L)) {
-    if (x == L) {
-      x = 0.0f;
-    } else if (isfinite(x)) {
-      x = x - L * floorf(x / L);
-      if (x >= L || x < 0.0f) x = 0.0f;
-    }
-  }
+  const float lo = x + L, hi = x - L;
+  x = x < 0.0f ? lo : (x >= L ? hi : x);
+  if (__builtin_expect(!(x >= 0.0f && x < L), 0)) x = wrap32_rare(x, L);
   return x;
 }
 
@@ -258,13 +256,10 @@ __device__ __forceinline__ uint32_t split_encode(const int (&c)[3]) {
   return (uint32_t)c[0] | ((uint32_t)c[1] << kSplitXBits) |
          ((uint32_t)c[2] << (kSplitXBits + kSplitYBits));
 }
+__device__ __noinline__ int wrap_cell_rare(int c, int L) { return ((c % L) + L) % L; }
 __device__ __forceinline__ int wrap_cell(int c, int L) {
-  if (c < 0) {
-    c += L;
-  } else if (c >= L) {
-    c -= L;
-  }
-  if (c < 0 || c >= L) c = ((c % L) + L) % L;
+  c = c < 0 ? c + L : (c >= L ? c - L : c);
+  if (__builtin_expect(c < 0 || c >= L, 0)) c = wrap_cell_rare(c, L);
   return c;
 }
 // FP64 value -> (cell, offset) with the offset rounded to FP32.
@@ -340,9 +335,17 @@ __device__ __forceinline__ void stream_split(uint32_t& cell, float (&o)[3], floa
   cell = split_encode(cn);
 }
 
+// c + L if c < 0, c - L if c >= L (c within one period of [0, L)); branch-free.
+__device__ __forceinline__ int wrap1(int c, int L) {
+  c += L & -(int)(c < 0);
+  c -= L & -(int)(c >= L);
+  return c;
+}
+
 // Shifted cell coordinates c_k = floor(x_k + s_k) of a position given as
 // integer part ci_k plus fraction xf_k in double (exact), with periodic wrap
 // (walls: z becomes the layer index c_z + 1 in [0, H+1]).  Invalid -> err.
+template <bool W>
 __device__ __forceinline__ bool coords_of(const int (&ci)[3], const double (&xf)[3],
                                           const double (&s)[3], BoxRef B, int (&c)[3],
                                           uint32_t& err) {
@@ -350,25 +353,20 @@ __device__ __forceinline__ bool coords_of(const int (&ci)[3], const double (&xf)
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const double y = xf[k] + s[k];
-    if (!(y >= -2.0 && y < (double)B.L[k] + 2.0)) {
-      ok = false;
-      c[k] = 0;
-    } else {
-      c[k] = ci[k] + (int)floor(y);
-    }
+    const bool in = y >= -2.0 && y < B.Ld[k] + 2.0;
+    ok = ok && in;
+    c[k] = ci[k] + (int)floor(in ? y : 0.0);
   }
-  if (ok) {
-    c[0] = c[0] < 0 ? c[0] + B.L[0] : (c[0] >= B.L[0] ? c[0] - B.L[0] : c[0]);
-    c[1] = c[1] < 0 ? c[1] + B.L[1] : (c[1] >= B.L[1] ? c[1] - B.L[1] : c[1]);
-    if (B.walls) {
-      c[2] += 1;
-    } else {
-      c[2] = c[2] < 0 ? c[2] + B.L[2] : (c[2] >= B.L[2] ? c[2] - B.L[2] : c[2]);
-    }
-    ok = c[0] >= 0 && c[0] < B.L[0] && c[1] >= 0 && c[1] < B.L[1] && c[2] >= 0 &&
-         c[2] < B.nlz;
+  c[0] = wrap1(c[0], B.L[0]);
+  c[1] = wrap1(c[1], B.L[1]);
+  if (W) {
+    c[2] += 1;
+  } else {
+    c[2] = wrap1(c[2], B.L[2]);
   }
-  if (!ok) {
+  ok = ok && (unsigned)c[0] < (unsigned)B.L[0] && (unsigned)c[1] < (unsigned)B.L[1] &&
+       (unsigned)c[2] < (unsigned)B.nlz;
+  if (__builtin_expect(!ok, 0)) {
     err |= kErrKey;
     c[0] = c[1] = c[2] = 0;
   }
@@ -379,10 +377,11 @@ __device__ __forceinline__ uint32_t linear_key(const int (&c)[3], BoxRef B) {
   return (uint32_t)((c[2] * B.L[1] + c[1]) * B.L[0] + c[0]);
 }
 
+template <bool W>
 __device__ __forceinline__ uint32_t key_of(const int (&ci)[3], const double (&xf)[3],
                                            const double (&s)[3], BoxRef B, uint32_t& err) {
   int c[3];
-  coords_of(ci, xf, s, B, c, err);
+  coords_of<W>(ci, xf, s, B, c, err);
   return linear_key(c, B);
 }
 
@@ -429,17 +428,19 @@ struct Form<kFormF64> {
   }
   template <bool W>
   __device__ static void stream(P& p, Vv& v, BoxRef B) { stream_f64<W>(p.x, v.v, B); }
+  template <bool W>
   __device__ static uint32_t key(const P& p, const double (&s)[3], BoxRef B,
                                  uint32_t& err) {
     const int ci[3] = {0, 0, 0};
     const double xf[3] = {p.x[0], p.x[1], p.x[2]};
-    return key_of(ci, xf, s, B, err);
+    return key_of<W>(ci, xf, s, B, err);
   }
+  template <bool W>
   __device__ static void coords(const P& p, const double (&s)[3], BoxRef B, int (&c)[3],
                                 uint32_t& err) {
     const int ci[3] = {0, 0, 0};
     const double xf[3] = {p.x[0], p.x[1], p.x[2]};
-    coords_of(ci, xf, s, B, c, err);
+    coords_of<W>(ci, xf, s, B, c, err);
   }
 };
 
@@ -481,17 +482,19 @@ struct Form<kFormF32> {
   }
   template <bool W>
   __device__ static void stream(P& p, Vv& v, BoxRef B) { stream_f32<W>(p.x, v.v, B); }
+  template <bool W>
   __device__ static uint32_t key(const P& p, const double (&s)[3], BoxRef B,
                                  uint32_t& err) {
     const int ci[3] = {0, 0, 0};
     const double xf[3] = {(double)p.x[0], (double)p.x[1], (double)p.x[2]};
-    return key_of(ci, xf, s, B, err);
+    return key_of<W>(ci, xf, s, B, err);
   }
+  template <bool W>
   __device__ static void coords(const P& p, const double (&s)[3], BoxRef B, int (&c)[3],
                                 uint32_t& err) {
     const int ci[3] = {0, 0, 0};
     const double xf[3] = {(double)p.x[0], (double)p.x[1], (double)p.x[2]};
-    coords_of(ci, xf, s, B, c, err);
+    coords_of<W>(ci, xf, s, B, c, err);
   }
 };
 
@@ -540,19 +543,21 @@ struct Form<kFormSplit> {
   __device__ static void stream(P& p, Vv& v, BoxRef B) {
     stream_split<W>(p.cell, p.o, v.v, B);
   }
+  template <bool W>
   __device__ static uint32_t key(const P& p, const double (&s)[3], BoxRef B,
                                  uint32_t& err) {
     int ci[3];
     split_decode(p.cell, ci);
     const double xf[3] = {(double)p.o[0], (double)p.o[1], (double)p.o[2]};
-    return key_of(ci, xf, s, B, err);
+    return key_of<W>(ci, xf, s, B, err);
   }
+  template <bool W>
   __device__ static void coords(const P& p, const double (&s)[3], BoxRef B, int (&c)[3],
                                 uint32_t& err) {
     int ci[3];
     split_decode(p.cell, ci);
     const double xf[3] = {(double)p.o[0], (double)p.o[1], (double)p.o[2]};
-    coords_of(ci, xf, s, B, c, err);
+    coords_of<W>(ci, xf, s, B, c, err);
   }
 };
 
@@ -624,7 +629,7 @@ __global__ __launch_bounds__(kThreads) void k_key_hist(Dev d) {
       typename Fm::Vv v;
       Fm::load(S, i, p, v);
       Fm::template stream<W>(p, v, B);
-      key = B.cbase + Fm::key(p, s, B, err);
+      key = B.cbase + Fm::template key<W>(p, s, B, err);
       d.key[i] = key;
     }
     wave_hist_add(d.hist, key, i < pend);
@@ -895,14 +900,18 @@ __device__ __forceinline__ void rotation_matrix(BoxRef B, const double (&n)[3], 
 // Sums and random draws of one cell, one thread per cell.  Velocities of the
 // cell's fluid particles are sv[k][b..e) in canonical order.
 template <int F, bool W, bool M>
-__device__ void cell_work(BoxRef B, uint64_t t, uint32_t lkey, double sz,
-                          const CellDraw* __restrict__ draws, uint32_t gkey,
+__device__ void cell_work(BoxRef B, uint64_t t, uint32_t lkey, double sz, const CellDraw& cd,
                           const typename Form<F>::Vs* __restrict__ sv0,
                           const typename Form<F>::Vs* __restrict__ sv1,
                           const typename Form<F>::Vs* __restrict__ sv2, uint32_t b, uint32_t e,
                           CellLds& out) {
   const uint32_t nf = e - b;
+  // cells that do not collide keep v exactly: V = 0, R = I in the update
   out.active = 0u;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) out.V[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) out.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
   if (nf == 0) return;
   int nph = 0;
   if (W) {
@@ -966,12 +975,11 @@ __device__ void cell_work(BoxRef B, uint64_t t, uint32_t lkey, double sz,
     V[1] = P[1] / Mtot;
     V[2] = P[2] / Mtot;
   }
+  if (ntot < 2) return;
   out.V[0] = V[0];
   out.V[1] = V[1];
   out.V[2] = V[2];
-  if (ntot < 2) return;
   out.active = 1u;
-  const CellDraw cd = draws[gkey];
   const double n[3] = {cd.n[0], cd.n[1], cd.n[2]};
   double kappa = 1.0;
   if (M && cd.Ek > 0.0) {
@@ -1002,6 +1010,28 @@ __device__ void cell_work(BoxRef B, uint64_t t, uint32_t lkey, double sz,
   rotation_matrix(B, n, kappa, out.R);
 }
 
+// The collide workgroup is a single wavefront.  LDS instructions of one wave
+// execute in issue order, so lanes see each other's LDS writes without a
+// hardware barrier; a wavefront-scope fence keeps the compiler from moving LDS
+// accesses across phase boundaries.  (A workgroup barrier would also wait for
+// every outstanding global load and store of the wave.)
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+// Tile index of the it-th work item of this workgroup (XCD-aware order:
+// workgroup b runs on XCD b % 8; each XCD takes a contiguous part of the tile
+// list, which the host ordered so that neighbouring rows are close in it).
+struct TileWalk {
+  uint32_t first, stride, per_xcd, xcd, ntiles;
+  __device__ uint32_t tile(uint32_t it) const {
+    if (per_xcd) {
+      if (it >= per_xcd) return 0xffffffffu;
+      const uint32_t t = xcd * per_xcd + it;
+      return t < ntiles ? t : 0xffffffffu;
+    }
+    return it < ntiles ? it : 0xffffffffu;
+  }
+};
+
 template <int F, bool W, bool M>
 __global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu(W ? 2 : 3)))
 void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
@@ -1010,7 +1040,8 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   using Xs = typename Fm::Xs;
   constexpr int NT = kCollideThreads;
   constexpr int NS = kTileCap / kCollideThreads;
-  static_assert(kTileMaxCells < NT, "one thread per cell offset (nc + 1) of a tile");
+  static_assert(kTileMaxCells < NT, "one lane per cell offset (nc + 1) of a tile");
+  static_assert(NT == 64, "the workgroup is one wavefront (see wave_sync)");
   __shared__ uint32_t s_off[kTileMaxCells + 1];
   __shared__ uint32_t s_idx[kTileCap];   // perm entries, segment order as scattered
   __shared__ uint32_t s_idxc[kTileCap];  // storage index at the canonical position
@@ -1031,37 +1062,47 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   const StatePtrs in = d.S[cur];
   const StatePtrs out = sorted ? d.S[cur ^ 1u] : d.S[cur];
   uint32_t err = 0;
+  const uint32_t lane = threadIdx.x;
 
-  // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a
-  // contiguous range of tiles so that neighbouring rows share its L2.
-  const uint32_t G = gridDim.x;
-  uint32_t first = blockIdx.x, stride = G;
-  uint32_t per_xcd = 0, xcd = 0;
-  if (xcd_remap && G % 8 == 0) {
-    xcd = blockIdx.x % 8;
-    per_xcd = (ntiles + 7) / 8;
-    first = blockIdx.x / 8;
-    stride = G / 8;
+  TileWalk walk;
+  walk.ntiles = ntiles;
+  walk.first = blockIdx.x;
+  walk.stride = gridDim.x;
+  walk.per_xcd = 0;
+  walk.xcd = 0;
+  if (xcd_remap && gridDim.x % 8 == 0) {
+    walk.xcd = blockIdx.x % 8;
+    walk.per_xcd = (ntiles + 7) / 8;
+    walk.first = blockIdx.x / 8;
+    walk.stride = gridDim.x / 8;
   }
-  uint32_t cached_box = 0xffffffffu;
-  uint32_t pf_tile = 0xffffffffu, pf_off = 0;  // prefetched offsets of the next tile
 
-  for (uint32_t it = first;; it += stride) {
-    uint32_t tile;
-    if (per_xcd) {
-      if (it >= per_xcd) break;
-      tile = xcd * per_xcd + it;
-      if (tile >= ntiles) break;
-    } else {
-      if (it >= ntiles) break;
-      tile = it;
-    }
-    const Tile T = load_tile(d.tiles, tile);
+  // Software pipeline over tiles: offsets are fetched two tiles ahead, the
+  // first pass's perm entries and the cell draws one tile ahead.
+  uint32_t it = walk.first;
+  uint32_t tcur = walk.tile(it);
+  uint32_t tnext = walk.tile(it + walk.stride);
+  uint32_t off_cur = 0, off_next = 0;
+  if (tcur != 0xffffffffu) {
+    const Tile Tc = load_tile(d.tiles, tcur);
+    if (lane <= Tc.nc) off_cur = d.offset[Tc.c0 + lane];
+  }
+  if (tnext != 0xffffffffu) {
+    const Tile Tn = load_tile(d.tiles, tnext);
+    if (lane <= Tn.nc) off_next = d.offset[Tn.c0 + lane];
+  }
+  uint32_t perm_cur[NS];
+  CellDraw draw_cur;
+  bool have_pf = false;  // perm_cur / draw_cur hold the current tile's data
+  uint32_t cached_box = 0xffffffffu;
+
+  for (; tcur != 0xffffffffu; it += walk.stride) {
+    const Tile T = load_tile(d.tiles, tcur);
     BoxRef B = as_const(d.boxes)[T.box];
-    __syncthreads();  // LDS of the previous tile is free
-    if (threadIdx.x <= T.nc)
-      s_off[threadIdx.x] = pf_tile == tile ? pf_off : d.offset[T.c0 + threadIdx.x];
-    if (threadIdx.x == 0 && T.box != cached_box) {
+    const uint32_t tafter = walk.tile(it + 2 * walk.stride);
+    wave_sync();  // LDS of the previous tile is free
+    if (lane <= T.nc) s_off[lane] = off_cur;
+    if (lane == 0 && T.box != cached_box) {
       double s0[3], s1[3];
       shift_of(B, t, s0);
       shift_of(B, t + 1, s1);
@@ -1079,8 +1120,19 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
     const int y0 = (int)((lkey0 / (uint32_t)B.L[0]) % (uint32_t)B.L[1]);
     const int z0 = (int)(lkey0 / (uint32_t)(B.L[0] * B.L[1]));
     const int WX = (int)T.nc + 2;
-    for (int i = threadIdx.x; i < 9 * WX; i += NT) s_hw[i] = 0u;
-    __syncthreads();
+    const int L0 = B.L[0], L1 = B.L[1], L2 = B.L[2];
+    for (int i = lane; i < 9 * WX; i += NT) s_hw[i] = 0u;
+    // offsets of the tile after next (two ahead)
+    uint32_t off_after = 0;
+    if (tafter != 0xffffffffu) {
+      const Tile Ta = load_tile(d.tiles, tafter);
+      if (lane <= Ta.nc) off_after = d.offset[Ta.c0 + lane];
+    }
+    wave_sync();
+
+    uint32_t perm_next[NS];
+    CellDraw draw_next;
+    bool issued_next = false;
 
     uint32_t cs = 0;
     while (cs < T.nc) {
@@ -1106,13 +1158,14 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
         break;
       }
       const uint32_t np = s_off[ce] - base;
+      const bool use_pf = have_pf && cs == 0;
 
       if (np > (uint32_t)kTileCap) {
         // one cell beyond capacity: stream and re-bin its particles unchanged
         err |= kErrCellOverflow;
         const double snx[3] = {s_sh[3], s_sh[4], s_sh[5]};
         for (uint32_t q0 = 0; q0 < np; q0 += NT) {
-          const uint32_t q = q0 + threadIdx.x;
+          const uint32_t q = q0 + lane;
           const uint32_t i = q < np ? d.perm[base + q] : d.ntot;
           const bool live = i < d.ntot;
           uint32_t kn = 0;
@@ -1124,48 +1177,61 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             const uint32_t j = sorted ? base + q : i;
             Fm::store(out, j, p, v);
             Fm::template stream<W>(p, v, B);
-            kn = B.cbase + Fm::key(p, snx, B, err);
+            kn = B.cbase + Fm::template key<W>(p, snx, B, err);
             d.key[j] = kn;
           }
           wave_hist_add(d.hist, kn, live);
         }
         cs = ce;
-        __syncthreads();
+        wave_sync();
         continue;
       }
 
-      // Phase A: segment entries and their local cell
+      // Phase A: segment entries (prefetched for the first pass) and their cell
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
-        const uint32_t q = threadIdx.x + k * NT;
-        if (q < np) s_idx[q] = d.perm[base + q];
+        const uint32_t q = lane + k * NT;
+        if (q < np) s_idx[q] = use_pf ? perm_cur[k] : d.perm[base + q];
       }
-      if (cs + threadIdx.x < ce) {
-        const uint32_t c = cs + threadIdx.x;
+      if (cs + lane < ce) {
+        const uint32_t c = cs + lane;
         const uint32_t b = s_off[c] - base, e = s_off[c + 1] - base;
         for (uint32_t q = b; q < e; ++q) s_lc[q] = (uint8_t)(c - cs);
       }
-      __syncthreads();
+      wave_sync();
 
       // Phase B: gather, canonical position (rank by storage index inside
-      // the cell), stream of step t, park in LDS.  All gathers are issued
-      // first; the slots are then finished one after the other.
+      // the cell), stream of step t, park in LDS.
       {
         typename Fm::P p[NS];
         typename Fm::Vv v[NS];
         uint32_t ii[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-          const uint32_t q = threadIdx.x + k * NT;
+          const uint32_t q = lane + k * NT;
           ii[k] = 0;
           if (q < np) {
             ii[k] = s_idx[q] < d.ntot ? s_idx[q] : 0u;
             Fm::load(in, ii[k], p[k], v[k]);
           }
         }
+        // prefetch the next tile's first-pass perm entries and cell draws
+        if (!issued_next && tnext != 0xffffffffu) {
+          issued_next = true;
+          const Tile Tn = load_tile(d.tiles, tnext);
+          const uint32_t nb = (uint32_t)__builtin_amdgcn_readfirstlane((int)off_next);
+          const uint32_t ne = (uint32_t)__builtin_amdgcn_readlane((int)off_next, Tn.nc);
+          const uint32_t nn = ne >= nb ? ne - nb : 0u;
+#pragma unroll
+          for (int k = 0; k < NS; ++k) {
+            const uint32_t q = lane + k * NT;
+            perm_next[k] = (q < nn && nb + q < d.ntot) ? d.perm[nb + q] : 0u;
+          }
+          if (lane < Tn.nc) draw_next = d.draws[Tn.c0 + lane];
+        }
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-          const uint32_t q = threadIdx.x + k * NT;
+          const uint32_t q = lane + k * NT;
           __builtin_amdgcn_sched_barrier(0);
           if (q < np) {
             const uint32_t i = ii[k];
@@ -1181,40 +1247,32 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
           }
         }
       }
-      __syncthreads();
+      wave_sync();
 
-      // Phase C: one thread per cell (first pass of a tile also prefetches the
-      // next tile's offsets)
-      if (cs == 0) {
-        const uint32_t itn = it + stride;
-        uint32_t tn = 0xffffffffu;
-        if (per_xcd) {
-          if (itn < per_xcd && xcd * per_xcd + itn < ntiles) tn = xcd * per_xcd + itn;
-        } else if (itn < ntiles) {
-          tn = itn;
-        }
-        pf_tile = tn;
-        if (tn != 0xffffffffu) {
-          const Tile Tn = load_tile(d.tiles, tn);
-          if (threadIdx.x <= Tn.nc) pf_off = d.offset[Tn.c0 + threadIdx.x];
-        }
-      }
-      if (cs + threadIdx.x < ce) {
-        const uint32_t c = cs + threadIdx.x;
+      // Phase C: one lane per cell (the first pass uses the prefetched draws)
+      if (cs + lane < ce) {
+        const uint32_t c = cs + lane;
         const uint32_t b = s_off[c] - base, e = s_off[c + 1] - base;
-        cell_work<F, W, M>(B, t, lkey0 + c, s_sh[2], d.draws, T.c0 + c, s_v[0], s_v[1], s_v[2], b, e,
+        CellDraw cd;
+        if (use_pf) {
+          cd = draw_cur;
+        } else if (e > b) {
+          cd = d.draws[T.c0 + c];
+        } else {
+          cd.n[0] = cd.n[1] = cd.n[2] = 0.0;
+          cd.Ek = 0.0;
+        }
+        cell_work<F, W, M>(B, t, lkey0 + c, s_sh[2], cd, s_v[0], s_v[1], s_v[2], b, e,
                            s_cell[c - cs]);
       }
-      __syncthreads();
+      wave_sync();
 
       // Phase D: rotate + scale, gravity, write, stream + bin step t+1
       const double snext[3] = {s_sh[3], s_sh[4], s_sh[5]};
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
-        const uint32_t q = threadIdx.x + k * NT;
+        const uint32_t q = lane + k * NT;
         __builtin_amdgcn_sched_barrier(0);
-        uint32_t kn = 0;
-        bool live = false;
         if (q < np) {
           typename Fm::P p;
           typename Fm::Vv v;
@@ -1224,7 +1282,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
           v.v[2] = s_v[2][q];
           const CellLds& C = s_cell[s_lc[q]];
           if constexpr (F == kFormSplit) {
-            if (C.active) {
+            {
               const float V[3] = {(float)C.V[0], (float)C.V[1], (float)C.V[2]};
               const float u[3] = {v.v[0] - V[0], v.v[1] - V[1], v.v[2] - V[2]};
 #pragma unroll
@@ -1240,11 +1298,12 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             }
           } else {
             double w[3] = {(double)v.v[0], (double)v.v[1], (double)v.v[2]};
-            if (C.active) {
+            {
               const double u[3] = {w[0] - C.V[0], w[1] - C.V[1], w[2] - C.V[2]};
 #pragma unroll
               for (int a = 0; a < 3; ++a)
-                w[a] = C.V[a] + fma(C.R[3 * a], u[0], fma(C.R[3 * a + 1], u[1], C.R[3 * a + 2] * u[2]));
+                w[a] = C.V[a] +
+                       fma(C.R[3 * a], u[0], fma(C.R[3 * a + 1], u[1], C.R[3 * a + 2] * u[2]));
             }
             if (B.grav) {
 #pragma unroll
@@ -1258,30 +1317,20 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             Fm::store(out, j, p, v);
             Fm::template stream<W>(p, v, B);
             int c[3];
-            Fm::coords(p, snext, B, c, err);
-            kn = B.cbase + linear_key(c, B);
+            Fm::template coords<W>(p, snext, B, c, err);
+            const uint32_t kn = B.cbase + linear_key(c, B);
             d.key[j] = kn;
-            int dx = c[0] - x0 + 1;
-            if (dx < 0) {
-              dx += B.L[0];
-            } else if (dx >= B.L[0]) {
-              dx -= B.L[0];
-            }
+            const int dx = wrap1(c[0] - x0 + 1, L0);
             int dy = c[1] - y0;
-            if (dy > 1) {
-              dy -= B.L[1];
-            } else if (dy < -1) {
-              dy += B.L[1];
-            }
+            dy += L1 & -(int)(dy < -1);
+            dy -= L1 & -(int)(dy > 1);
             int dz = c[2] - z0;
             if (!W) {
-              if (dz > 1) {
-                dz -= B.L[2];
-              } else if (dz < -1) {
-                dz += B.L[2];
-              }
+              dz += L2 & -(int)(dz < -1);
+              dz -= L2 & -(int)(dz > 1);
             }
-            if (dx < WX && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) {
+            if ((unsigned)dx < (unsigned)WX && (unsigned)(dy + 1) < 3u &&
+                (unsigned)(dz + 1) < 3u) {
               atomicAdd(&s_hw[((dz + 1) * 3 + (dy + 1)) * WX + dx], 1u);
             } else {
               atomicAdd(&d.hist[kn], 1u);
@@ -1290,37 +1339,49 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             err |= kErrKey;
           }
         }
-        (void)live;
-        (void)kn;
       }
       cs = ce;
-      __syncthreads();
+      wave_sync();
     }
     // flush the tile's window into the global histogram
-    for (int i = threadIdx.x; i < 9 * WX; i += NT) {
-      const uint32_t cnt = s_hw[i];
-      if (cnt) {
-        const int dzi = i / (3 * WX), dyi = (i / WX) % 3, dx = i % WX;
-        int c[3] = {x0 - 1 + dx, y0 + dyi - 1, z0 + dzi - 1};
-        if (c[0] < 0) {
-          c[0] += B.L[0];
-        } else if (c[0] >= B.L[0]) {
-          c[0] -= B.L[0];
-        }
-        if (c[1] < 0) {
-          c[1] += B.L[1];
-        } else if (c[1] >= B.L[1]) {
-          c[1] -= B.L[1];
-        }
-        if (!W) {
-          if (c[2] < 0) {
-            c[2] += B.L[2];
-          } else if (c[2] >= B.L[2]) {
-            c[2] -= B.L[2];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      const int dzi = r / 3, dyi = r % 3;
+      for (int dx = lane; dx < WX; dx += NT) {
+        const uint32_t cnt = s_hw[r * WX + dx];
+        if (cnt) {
+          int c[3] = {x0 - 1 + dx, y0 + dyi - 1, z0 + dzi - 1};
+          if (c[0] < 0) {
+            c[0] += B.L[0];
+          } else if (c[0] >= B.L[0]) {
+            c[0] -= B.L[0];
           }
+          if (c[1] < 0) {
+            c[1] += B.L[1];
+          } else if (c[1] >= B.L[1]) {
+            c[1] -= B.L[1];
+          }
+          if (!W) {
+            if (c[2] < 0) {
+              c[2] += B.L[2];
+            } else if (c[2] >= B.L[2]) {
+              c[2] -= B.L[2];
+            }
+          }
+          atomicAdd(&d.hist[B.cbase + linear_key(c, B)], cnt);
         }
-        atomicAdd(&d.hist[B.cbase + linear_key(c, B)], cnt);
       }
+    }
+    // advance the pipeline
+    tcur = tnext;
+    tnext = tafter;
+    off_cur = off_next;
+    off_next = off_after;
+    have_pf = issued_next;
+    if (issued_next) {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) perm_cur[k] = perm_next[k];
+      draw_cur = draw_next;
     }
   }
   if (err) atomicOr(&d.ctrl->err, err);
