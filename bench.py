@@ -4,13 +4,18 @@
 Prints ONE JSON line.  `value` is FP64 particle-steps/s on the 256^3 periodic
 box with the Maxwell-Boltzmann-scaling thermostat, 10 particles per cell and
 particles reordered by cell every 20 steps (inputs resident in HBM before the
-timed region).  The same line carries:
+timed region; 200 steps by default).  The same line carries:
   roofline     : the collide kernel (dominant) -- algorithmic bytes per launch
                  (particles x state bytes read + written once) / its average
-                 duration from HIP events on the launch stream;
-  forms        : FP32 and split-FP32 on the same box, and the batched
-                 ensemble of 64 uneven boxes (graph replay);
+                 duration from HIP events on the launch stream; `traffic` is
+                 the HBM bytes per launch from rocprofv3 counter runs of this
+                 same command, when they were taken on the current kernels;
+  forms        : FP32 and split-FP32 on the same box, FP64 stored in cell
+                 order after every step, and the batched ensemble of 64
+                 uneven boxes (graph replay);
   cpu_baseline : the single-threaded CPU oracle on a bounded sample.
+--copy-probe-gib G adds one device-to-device copy of G GiB before the run: the
+counter runs use it to scale FETCH_SIZE / WRITE_SIZE to bytes.
 """
 from __future__ import annotations
 
@@ -38,7 +43,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_record(form: str, workload: str):
+def traffic_record(form: str, workload: str, R: int):
     """HBM bytes per collide launch from committed rocprofv3 counter runs, if
     they were taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "collide_hbm_traffic.json")
@@ -47,7 +52,7 @@ def traffic_record(form: str, workload: str):
             rec = json.load(f)
     except OSError:
         return None
-    r = rec.get(f"{workload}:{form}")
+    r = rec.get(f"{workload}:{form}:R{R}")
     if not r or r.get("kernel_hash") != kernel_source_hash():
         return None
     return r
@@ -111,10 +116,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--forms", default="fp32,split,batched",
+    ap.add_argument("--forms", default="fp32,split,fp64_sorted_every_step,batched",
                     help="extra entries besides the FP64 headline (comma list, or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=500)
+    ap.add_argument("--reorder-every", type=int, default=20)
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -127,15 +134,34 @@ def main():
     mpc.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    copy_probe = None
+    if args.copy_probe_gib > 0:
+        nb = int(args.copy_probe_gib * 2 ** 30)
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        copy_probe = {"bytes_read": nb, "bytes_written": nb, "ms": ms,
+                      "GBs": 2 * nb / (ms * 1e-3) / 1e9}
+        del src, dst
+        torch.cuda.empty_cache()
+
     box = synth.config("C2")
     workload = "C2"
-    n, wall, kt, obs = run_box(mpc, torch, box, "fp64", 20, args.steps, args.warmup)
+    R = args.reorder_every
+    n, wall, kt, obs = run_box(mpc, torch, box, "fp64", R, args.steps, args.warmup)
     value = n * args.steps / wall
     ms_step = wall * 1e3 / args.steps
     coll_ms = kt.collide_ms / max(1, kt.collide_launches)
     alg_bytes = n * 2 * STATE_BYTES["fp64"]
     achieved = alg_bytes / (coll_ms * 1e-3) / 1e9
-    tr = traffic_record("fp64", workload)
+    tr = traffic_record("fp64", workload, R)
     print(f"[fp64 C2] N={n} {ms_step:.3f} ms/step: scan {kt.scan_ms / args.steps:.3f} "
           f"scatter {kt.scatter_ms / args.steps:.3f} collide {coll_ms:.3f} "
           f"other {kt.other_ms / args.steps:.3f} ms; T={obs['T']:.4f}", file=sys.stderr)
@@ -146,8 +172,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "256^3 periodic cells, 10 particles/cell "
                                f"({n} particles), MBS thermostat, kT=1, h=0.1, "
-                               "alpha=130deg, FP64 SoA, reorder every 20 steps",
-                   "particles": n, "cells": 256 ** 3},
+                               f"alpha=130deg, FP64 SoA, reorder every {R} steps",
+                   "particles": n, "cells": 256 ** 3, "reorder_every": R},
         "hbm_roofline_frac_step": value * 2 * STATE_BYTES["fp64"] / (HBM_PEAK_GBS * 1e9),
         "roofline": {"bound": "hbm", "kernel": "k_collide<fp64>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -163,16 +189,29 @@ def main():
     for form in extra:
         try:
             if form in ("fp32", "split"):
-                n2, w2, k2, o2 = run_box(mpc, torch, box, form, 20, args.steps, args.warmup)
+                n2, w2, k2, o2 = run_box(mpc, torch, box, form, R, args.steps, args.warmup)
                 v2 = n2 * args.steps / w2
                 c2 = k2.collide_ms / max(1, k2.collide_launches)
                 forms[form] = {
-                    "workload": "same 256^3 box", "value": v2, "unit": "particle-steps/s",
+                    "workload": f"same 256^3 box, reorder every {R} steps", "value": v2, "unit": "particle-steps/s",
                     "ms_per_step": w2 * 1e3 / args.steps,
                     "hbm_roofline_frac_step": v2 * 2 * STATE_BYTES[form] / (HBM_PEAK_GBS * 1e9),
                     "collide_ms": c2,
                     "collide_achieved_GBs": n2 * 2 * STATE_BYTES[form] / (c2 * 1e-3) / 1e9}
                 print(f"[{form} C2] {w2 * 1e3 / args.steps:.3f} ms/step collide {c2:.3f} ms",
+                      file=sys.stderr)
+            elif form == "fp64_sorted_every_step":
+                n2, w2, k2, o2 = run_box(mpc, torch, box, "fp64", 1, args.steps, args.warmup)
+                v2 = n2 * args.steps / w2
+                c2 = k2.collide_ms / max(1, k2.collide_launches)
+                forms[form] = {
+                    "workload": "same 256^3 box, FP64, state written in cell order every step",
+                    "value": v2, "unit": "particle-steps/s",
+                    "ms_per_step": w2 * 1e3 / args.steps,
+                    "hbm_roofline_frac_step": v2 * 2 * STATE_BYTES["fp64"] / (HBM_PEAK_GBS * 1e9),
+                    "collide_ms": c2,
+                    "collide_achieved_GBs": n2 * 2 * STATE_BYTES["fp64"] / (c2 * 1e-3) / 1e9}
+                print(f"[fp64 R=1 C2] {w2 * 1e3 / args.steps:.3f} ms/step collide {c2:.3f} ms",
                       file=sys.stderr)
             elif form == "batched":
                 boxes = synth.batch_boxes(64, seed=4)
@@ -192,6 +231,8 @@ def main():
             forms[form] = {"error": str(exc)}
     if forms:
         line["forms"] = forms
+    if copy_probe:
+        line["copy_probe"] = copy_probe
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -35,7 +35,8 @@ struct Plan {
   size_t state_elem_a = 0, state_elem_b = 0;  // bytes per component
   bool split = false;
   // byte offsets in the workspace
-  size_t off_S[2][7] = {};
+  size_t off_S[2][8] = {};
+  bool ids = false;  // logical-index arrays (reorder interval other than 1)
   size_t off_key = 0, off_perm = 0, off_hist = 0, off_offset = 0, off_scan = 0, off_ctrl = 0,
          off_boxes = 0, off_tiles = 0, off_pblocks = 0, off_partials = 0, off_vmean = 0,
          off_draws = 0;
@@ -117,6 +118,7 @@ int make_plan(const mpc_params* p, int32_t nbox, Plan& P, std::string* why) {
   }
   const int form = p[0].form;
   P.split = form == MPC_SPLIT32;
+  P.ids = p[0].reorder_every != 1;
   P.state_elem_a = form == MPC_FP64 ? 8 : 4;
   P.state_elem_b = form == MPC_FP64 ? 8 : 4;
   size_t off = 0;
@@ -129,6 +131,7 @@ int make_plan(const mpc_params* p, int32_t nbox, Plan& P, std::string* why) {
     for (int k = 0; k < 3; ++k) P.off_S[s][k] = take(P.state_elem_a * P.ntot);
     for (int k = 0; k < 3; ++k) P.off_S[s][3 + k] = take(P.state_elem_b * P.ntot);
     P.off_S[s][6] = P.split ? take(4 * P.ntot) : 0;
+    P.off_S[s][7] = P.ids ? take(4 * P.ntot) : 0;
   }
   P.off_key = take(4 * P.ntot);
   P.off_perm = take(4 * P.ntot);
@@ -303,11 +306,8 @@ int ensure_keys(mpc_sim* s) {
 }
 
 void advance_mirror(mpc_sim* s, int64_t n) {
-  for (int64_t k = 0; k < n; ++k) {
-    const uint64_t t = s->step;
-    if (s->R > 0 && (t + 1) % (uint64_t)s->R == 0) s->cur ^= 1u;
-    s->step = t + 1;
-  }
+  s->cur ^= (uint32_t)(n & 1);
+  s->step += (uint64_t)n;
 }
 
 int drop_graph(mpc_sim* s) {
@@ -442,6 +442,7 @@ int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
       s->dev.S[b].b[k] = ws + P.off_S[b][3 + k];
     }
     s->dev.S[b].cell = P.split ? (uint32_t*)(ws + P.off_S[b][6]) : nullptr;
+    s->dev.S[b].id = P.ids ? (uint32_t*)(ws + P.off_S[b][7]) : nullptr;
   }
   s->dev.key = (uint32_t*)(ws + P.off_key);
   s->dev.perm = (uint32_t*)(ws + P.off_perm);
@@ -783,6 +784,12 @@ int mpc_set_state(mpc_sim* s, int32_t box, const double* x, const double* v, int
     }
     if (!rc) rc = copy_h2d(s, S.cell, B.pbase, cell);
   }
+  if (!rc && S.id) {
+    std::vector<uint32_t> ids(n);
+    for (int64_t i = 0; i < n; ++i) ids[i] = B.pbase + (uint32_t)i;
+    rc = copy_h2d(s, S.id, B.pbase, ids);
+    if (!rc) HIPCHK(s, hipStreamSynchronize(s->L.stream));
+  }
   if (rc) return rc;
   HIPCHK(s, launch_set_ctrl(s->dev, s->L, s->step, s->cur, s->R, 1));
   HIPCHK(s, hipStreamSynchronize(s->L.stream));
@@ -799,13 +806,31 @@ int mpc_get_state(mpc_sim* s, int32_t box, double* x, double* v, int64_t n) {
   if (rc) return rc;
   const double a = s->params[box].a;
   const StatePtrs& S = s->dev.S[s->cur];
+  // logical index of each stored slot of the box
+  std::vector<uint32_t> lid(n);
+  if (S.id) {
+    if ((rc = copy_d2h(s, S.id, B.pbase, lid))) return rc;
+    HIPCHK(s, hipStreamSynchronize(s->L.stream));
+    std::vector<uint8_t> seen(n, 0);
+    for (int64_t i = 0; i < n; ++i) {
+      const uint32_t q = lid[i] - B.pbase;
+      if (lid[i] < B.pbase || q >= (uint64_t)n || seen[q]) {
+        s->err = "logical particle indices are not a permutation";
+        return MPC_ESTATE;
+      }
+      seen[q] = 1;
+      lid[i] = q;
+    }
+  } else {
+    for (int64_t i = 0; i < n; ++i) lid[i] = (uint32_t)i;
+  }
   if (s->form == MPC_FP64) {
     std::vector<double> buf(n);
     for (int k = 0; k < 6; ++k) {
       if ((rc = copy_d2h(s, k < 3 ? S.a[k] : S.b[k - 3], B.pbase, buf))) return rc;
       HIPCHK(s, hipStreamSynchronize(s->L.stream));
       double* dst = k < 3 ? x + k * n : v + (k - 3) * n;
-      for (int64_t i = 0; i < n; ++i) dst[i] = buf[i] * a;
+      for (int64_t i = 0; i < n; ++i) dst[lid[i]] = buf[i] * a;
     }
   } else {
     std::vector<float> buf(n);
@@ -823,9 +848,9 @@ int mpc_get_state(mpc_sim* s, int32_t box, double* x, double* v, int64_t n) {
         const uint32_t shift = k == 0 ? 0 : (k == 1 ? kSplitXBits : kSplitXBits + kSplitYBits);
         const uint32_t mask = k == 2 ? ((1u << kSplitZBits) - 1) : ((1u << kSplitXBits) - 1);
         for (int64_t i = 0; i < n; ++i)
-          dst[i] = ((double)((cell[i] >> shift) & mask) + (double)buf[i]) * a;
+          dst[lid[i]] = ((double)((cell[i] >> shift) & mask) + (double)buf[i]) * a;
       } else {
-        for (int64_t i = 0; i < n; ++i) dst[i] = (double)buf[i] * a;
+        for (int64_t i = 0; i < n; ++i) dst[lid[i]] = (double)buf[i] * a;
       }
     }
   }
@@ -861,15 +886,32 @@ int mpc_get_binning(mpc_sim* s, int32_t box, uint32_t* key, uint32_t* perm, uint
   }
   int rc = mpc_sync(s);
   if (rc) return rc;
-  HIPCHK(s, launch_canon_perm(s->dev, s->L));
+  // the last step read the buffer that is not current; its ids give the
+  // logical order before that step
+  const uint32_t* ids_in = s->dev.S[s->cur ^ 1u].id;
+  HIPCHK(s, launch_canon_perm(s->dev, s->L, ids_in));
   const BoxDev& B = s->boxes[box];
-  std::vector<uint32_t> off(B.nc + 1), pm(B.np);
+  std::vector<uint32_t> off(B.nc + 1), pm(B.np), lid;
   if ((rc = copy_d2h(s, s->dev.offset, B.cbase, off))) return rc;
   if ((rc = copy_d2h(s, s->dev.perm, B.pbase, pm))) return rc;
+  if (ids_in) {
+    lid.resize(B.np);
+    if ((rc = copy_d2h(s, ids_in, B.pbase, lid))) return rc;
+  }
   HIPCHK(s, hipStreamSynchronize(s->L.stream));
   const uint32_t o0 = off[0];
   for (auto& o : off) o -= o0;
-  for (auto& q : pm) q -= B.pbase;
+  for (auto& q : pm) {
+    if (q < B.pbase || q - B.pbase >= B.np) {
+      s->err = "permutation entry outside the box";
+      return MPC_ESTATE;
+    }
+    q = ids_in ? lid[q - B.pbase] - B.pbase : q - B.pbase;
+    if (q >= B.np) {
+      s->err = "logical particle index outside the box";
+      return MPC_ESTATE;
+    }
+  }
   if (offset) memcpy(offset, off.data(), sizeof(uint32_t) * off.size());
   if (perm) memcpy(perm, pm.data(), sizeof(uint32_t) * pm.size());
   if (key) {

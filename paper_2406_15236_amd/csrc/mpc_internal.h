@@ -58,7 +58,7 @@ struct PBlock {        // one block of a per-particle kernel
 
 struct Ctrl {          // device-resident step state, read by every kernel
   uint64_t step;       // step index t of the next step
-  uint32_t cur;        // which state buffer holds the current state
+  uint32_t cur;        // which state buffer holds the current state (flips every step)
   uint32_t err;        // sticky error bits
   int32_t reorder;     // R
   uint32_t pad[3];
@@ -71,10 +71,15 @@ struct CellDraw {       // random draws of one cell for the current step
 
 // State buffers of one form, SoA.  F64: a[0..2]=x (double), b[0..2]=v (double);
 // F32: x, v float; Split: cell (u32), a = offsets (float), b = v (float).
+// Every step writes the state in cell order into the other buffer.  `id` holds
+// each stored particle's logical index (its index in the caller's order, which
+// is renumbered to the stored order only on reorder steps); it is null when
+// every step is a reorder step (R = 1): the logical index is then the slot.
 struct StatePtrs {
   void* a[3];
   void* b[3];
   uint32_t* cell;
+  uint32_t* id;
 };
 
 struct Dev {           // device pointers carved from the workspace
@@ -117,7 +122,7 @@ hipError_t launch_init_state(const Dev& d, const Launch& l, uint64_t seed);
 hipError_t launch_obs_pass1(const Dev& d, const Launch& l);
 hipError_t launch_obs_pass2(const Dev& d, const Launch& l, const double* vmean_dev);
 hipError_t launch_remove_mean(const Dev& d, const Launch& l, const double* vmean_dev);
-hipError_t launch_canon_perm(const Dev& d, const Launch& l);
+hipError_t launch_canon_perm(const Dev& d, const Launch& l, const uint32_t* ids);
 hipError_t collide_occupancy(int form, int walls, int mbs, int* blocks_per_cu);
 
 }  // namespace mpc

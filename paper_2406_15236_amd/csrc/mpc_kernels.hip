@@ -577,10 +577,8 @@ __global__ void k_set_ctrl(Ctrl* c, uint64_t step, uint32_t cur, int32_t reorder
 }
 
 __global__ void k_advance(Ctrl* c) {
-  const uint64_t t = c->step;
-  const int32_t R = c->reorder;
-  if (R > 0 && (t + 1) % (uint64_t)R == 0) c->cur ^= 1u;
-  c->step = t + 1;
+  c->cur ^= 1u;
+  c->step = c->step + 1;
 }
 
 // hist[c] += 1 for every active lane, one atomic per distinct key in the
@@ -1044,7 +1042,8 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   static_assert(NT == 64, "the workgroup is one wavefront (see wave_sync)");
   __shared__ uint32_t s_off[kTileMaxCells + 1];
   __shared__ uint32_t s_idx[kTileCap];   // perm entries, segment order as scattered
-  __shared__ uint32_t s_idxc[kTileCap];  // storage index at the canonical position
+  __shared__ uint32_t s_rk[kTileCap];    // logical index of each entry (ids tracked)
+  __shared__ uint32_t s_idc[kTileCap];   // logical index at the canonical position
   __shared__ uint8_t s_lc[kTileCap];     // local cell of each slot
   __shared__ Vs s_v[3][kTileCap];        // streamed velocities, canonical order
   __shared__ Xs s_x[3][kTileCap];        // streamed positions (offsets), canonical order
@@ -1058,9 +1057,12 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   const uint64_t t = as_const(d.ctrl)->step;
   const uint32_t cur = as_const(d.ctrl)->cur;
   const int32_t R = as_const(d.ctrl)->reorder;
-  const bool sorted = R > 0 && (t + 1) % (uint64_t)R == 0;
+  // the state is always written in cell order into the other buffer; logical
+  // indices are renumbered to that order on reorder steps
+  const bool renumber = R > 0 && (t + 1) % (uint64_t)R == 0;
   const StatePtrs in = d.S[cur];
-  const StatePtrs out = sorted ? d.S[cur ^ 1u] : d.S[cur];
+  const StatePtrs out = d.S[cur ^ 1u];
+  const bool track = in.id != nullptr;
   uint32_t err = 0;
   const uint32_t lane = threadIdx.x;
 
@@ -1174,8 +1176,9 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             typename Fm::Vv v;
             Fm::load(in, i, p, v);
             Fm::template stream<W>(p, v, B);
-            const uint32_t j = sorted ? base + q : i;
+            const uint32_t j = base + q;
             Fm::store(out, j, p, v);
+            if (track) out.id[j] = renumber ? j : in.id[i];
             Fm::template stream<W>(p, v, B);
             kn = B.cbase + Fm::template key<W>(p, snx, B, err);
             d.key[j] = kn;
@@ -1187,11 +1190,16 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
         continue;
       }
 
-      // Phase A: segment entries (prefetched for the first pass) and their cell
+      // Phase A: segment entries (prefetched for the first pass), their
+      // logical indices and their cell
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
         const uint32_t q = lane + k * NT;
-        if (q < np) s_idx[q] = use_pf ? perm_cur[k] : d.perm[base + q];
+        if (q < np) {
+          const uint32_t pe = use_pf ? perm_cur[k] : d.perm[base + q];
+          s_idx[q] = pe;
+          if (track) s_rk[q] = pe < d.ntot ? in.id[pe] : 0u;
+        }
       }
       if (cs + lane < ce) {
         const uint32_t c = cs + lane;
@@ -1237,13 +1245,14 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             const uint32_t i = ii[k];
             const uint32_t c = cs + s_lc[q];
             const uint32_t b = s_off[c] - base, e = s_off[c + 1] - base;
-            const uint32_t qc = b + rank_in_segment(s_idx, b, e, i);
+            const uint32_t id = track ? s_rk[q] : i;
+            const uint32_t qc = b + rank_in_segment(track ? s_rk : s_idx, b, e, id);
             Fm::template stream<W>(p[k], v[k], B);
             Fm::to_lds(p[k], s_x[0], s_x[1], s_x[2], s_c, qc);
             s_v[0][qc] = v[k].v[0];
             s_v[1][qc] = v[k].v[1];
             s_v[2][qc] = v[k].v[2];
-            s_idxc[qc] = i;
+            s_idc[qc] = id;
           }
         }
       }
@@ -1312,9 +1321,10 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) v.v[a] = (Vs)w[a];
           }
-          const uint32_t j = sorted ? base + q : s_idxc[q];
+          const uint32_t j = base + q;
           if (j < d.ntot) {
             Fm::store(out, j, p, v);
+            if (track) out.id[j] = renumber ? j : s_idc[q];
             Fm::template stream<W>(p, v, B);
             int c[3];
             Fm::template coords<W>(p, snext, B, c, err);
@@ -1411,18 +1421,21 @@ hipError_t collide_occupancy(int form, int walls, int mbs, int* blocks_per_cu) {
 }
 
 // ---------------------------------------------------------------------------
-// Canonical permutation for export: sort each cell segment by storage index.
+// Canonical permutation for export: sort each cell segment by logical index
+// (ids[slot], or the slot itself when ids is null).
 // ---------------------------------------------------------------------------
 __global__ void k_canon_perm(uint32_t* __restrict__ perm, const uint32_t* __restrict__ offset,
-                             uint64_t ncell, uint32_t n) {
+                             uint64_t ncell, uint32_t n, const uint32_t* __restrict__ ids) {
   const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
   const uint32_t b = offset[c], e = offset[c + 1];
   if (e > n || b > e) return;
+  auto rk = [&](uint32_t slot) { return ids && slot < n ? ids[slot] : slot; };
   for (uint32_t i = b + 1; i < e; ++i) {
     const uint32_t x = perm[i];
+    const uint32_t kx = rk(x);
     uint32_t j = i;
-    while (j > b && perm[j - 1] > x) {
+    while (j > b && rk(perm[j - 1]) > kx) {
       perm[j] = perm[j - 1];
       --j;
     }
@@ -1444,6 +1457,7 @@ __global__ __launch_bounds__(kThreads) void k_init_state(Dev d, uint32_t k0, uin
     const uint32_t i = pb.p0 + s * kThreads + threadIdx.x;
     if (i >= pend) continue;
     const uint32_t li = i - B.pbase;
+    if (S.id) S.id[i] = i;
     const Words4 a = philox10(0, li, pb.box, kTagInitPos, k0, k1);
     const Words4 b = philox10(1, li, pb.box, kTagInitPos, k0, k1);
     double x[3] = {u53_of(a.w[0], a.w[1]) * B.Ld[0], u53_of(a.w[2], a.w[3]) * B.Ld[1],
@@ -1680,11 +1694,11 @@ hipError_t launch_collide(const Dev& d, const Launch& l) {
   return hipGetLastError();
 }
 
-hipError_t launch_canon_perm(const Dev& d, const Launch& l) {
+hipError_t launch_canon_perm(const Dev& d, const Launch& l, const uint32_t* ids) {
   const uint64_t blocks = (l.ctot + kThreads - 1) / kThreads;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_canon_perm, dim3((uint32_t)blocks), dim3(kThreads), 0, l.stream, d.perm,
-                     d.offset, l.ctot, (uint32_t)l.ntot);
+                     d.offset, l.ctot, (uint32_t)l.ntot, ids);
   return hipGetLastError();
 }
 

@@ -167,6 +167,34 @@ def test_reduced_precision_one_step(mpc, form, walls, R):
     assert e.max() <= 2e-6
 
 
+@pytest.mark.parametrize("R", [0, 3, 20])
+def test_fp64_multi_step_logical_order(mpc, R):
+    """The state is stored in cell order after every step; the caller's order
+    (renumbered only on reorder steps) must equal the oracle's storage order
+    over several reorder periods."""
+    box = box_of((11, 9, 10), mbs=True, seed=17)
+    x, v = synth.box_state(box["L"], seed=23)
+    steps = 7
+    print(f"case multi-step R={R}", flush=True)
+    with mpc.Sim(box, form="fp64", reorder_every=R) as sim:
+        sim.set_state(x, v)
+        sim.step(steps)
+        xg, vg = sim.get_state()
+        kg, pg, og = sim.get_binning()
+    p = oparams(box)
+    xo, vo = orc.run(p, x, v, steps - 1, reorder_every=R)
+    xo, vo, ko, po, oo = orc.step(p, steps - 1, xo, vo,
+                                  reorder=R > 0 and steps % R == 0, binning=True)
+    np.testing.assert_array_equal(kg, ko)
+    np.testing.assert_array_equal(pg, po)
+    np.testing.assert_array_equal(og, oo)
+    d = np.abs(xg - xo)
+    d = np.minimum(d, np.array(box["L"], float)[:, None] - d)
+    e = rel_err(vg, vo, box)
+    report(f"R={R} after {steps} steps", e)
+    assert d.max() < 1e-11 and e.max() < 1e-11
+
+
 def test_batched_parity(mpc):
     """Many uneven boxes advanced together equal each box stepped alone."""
     boxes = synth.batch_boxes(6, seed=4, lmin=6, lmax=15)
