@@ -179,9 +179,17 @@ int mpc_get_state(mpc_sim* s, int32_t box, double* x, double* v, int64_t n);
  * run since the state was set. */
 int mpc_get_binning(mpc_sim* s, int32_t box, uint32_t* key, uint32_t* perm, uint32_t* offset);
 
-/* Choose the collide launch (tile size, grid) by timing candidates on the
- * current state; the state, step counter and random streams are restored.
- * Returns the chosen configuration in *tile_cells and *grid (may be NULL). */
+/* Autotuner: choose the collide tiling (cells per tile, persistent grid size,
+ * rows per block of the tile order) by timing trial_steps steps (1..1000) of
+ * each candidate from the current state, in a coordinate search (tile size,
+ * then grid, then row block).  Before every trial and at the end the state
+ * and step counter are restored from a copy, so the random streams and all
+ * later results are exactly those of an untuned handle (results do not depend
+ * on the tiling).  The copy is one state buffer, in temporary device memory
+ * (pinned host memory if the device has no room).  Synchronises.  Returns the
+ * chosen tile size (0 = automatic per box) and grid in *tile_cells and *grid
+ * (either may be NULL).  Errors: MPC_EINVAL, MPC_EHIP, and sticky kernel
+ * errors of the state (MPC_ESTATE, MPC_ERANGE). */
 int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* grid);
 
 /* Override the collide tiling: cells per tile (4..32, 0 = automatic),

@@ -922,11 +922,129 @@ int mpc_get_binning(mpc_sim* s, int32_t box, uint32_t* key, uint32_t* perm, uint
 }
 
 int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* grid) {
-  if (!s || trial_steps < 1) return MPC_EINVAL;
-  (void)tile_cells;
-  (void)grid;
-  s->err = "autotune not available";
-  return MPC_EINVAL;
+  if (!s || trial_steps < 1 || trial_steps > 1000) return MPC_EINVAL;
+  int rc = mpc_sync(s);
+  if (rc) return rc;
+  const Plan& P = s->plan;
+  hipStream_t st = s->L.stream;
+  const uint64_t step0 = s->step;
+  const uint32_t cur0 = s->cur;
+  const int T0 = s->tile_override, g0 = s->grid_override, y0 = s->yblock;
+  // the arrays of the current state buffer, backed up on the device (or in
+  // host memory if the device has no room) and restored before every trial
+  std::vector<std::pair<void*, size_t>> arrs;
+  const StatePtrs& S = s->dev.S[cur0];
+  for (int k = 0; k < 3; ++k) arrs.push_back({S.a[k], P.state_elem_a * P.ntot});
+  for (int k = 0; k < 3; ++k) arrs.push_back({S.b[k], P.state_elem_b * P.ntot});
+  if (S.cell) arrs.push_back({S.cell, 4 * P.ntot});
+  if (S.id) arrs.push_back({S.id, 4 * P.ntot});
+  size_t total = 0;
+  for (auto& a : arrs) total += align256(a.second);
+  void* backup = nullptr;
+  bool on_host = false;
+  if (hipMalloc(&backup, total) != hipSuccess) {
+    (void)hipGetLastError();
+    backup = nullptr;
+    if (hipHostMalloc(&backup, total, hipHostMallocDefault) != hipSuccess) {
+      s->err = "autotune: no memory for the state backup";
+      return MPC_EHIP;
+    }
+    on_host = true;
+  }
+  auto copy_all = [&](bool save) -> hipError_t {
+    size_t o = 0;
+    for (auto& a : arrs) {
+      char* bk = (char*)backup + o;
+      hipError_t e = save ? hipMemcpyAsync(bk, a.first, a.second, hipMemcpyDefault, st)
+                          : hipMemcpyAsync(a.first, bk, a.second, hipMemcpyDefault, st);
+      if (e != hipSuccess) return e;
+      o += align256(a.second);
+    }
+    return hipStreamSynchronize(st);
+  };
+  auto release = [&]() {
+    if (on_host) {
+      (void)hipHostFree(backup);
+    } else {
+      (void)hipFree(backup);
+    }
+  };
+  auto restore = [&]() -> int {
+    hipError_t e = copy_all(false);
+    if (e != hipSuccess) return hip_fail(s, e, "autotune restore");
+    s->cur = cur0;
+    s->step = step0;
+    s->keys_valid = false;
+    s->have_binning = false;
+    HIPCHK(s, launch_set_ctrl(s->dev, s->L, step0, cur0, s->R, 1));
+    return MPC_OK;
+  };
+  hipError_t e0 = copy_all(true);
+  if (e0 != hipSuccess) {
+    release();
+    return hip_fail(s, e0, "autotune backup");
+  }
+  // one trial: set the tiling, one untimed step (binning prologue), then
+  // trial_steps timed steps; returns milliseconds per step
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  auto trial = [&](int T, int g, int yb, double* ms) -> int {
+    int r = mpc_set_tiling(s, T, g, yb);
+    if (r) return r;
+    if ((r = restore())) return r;
+    if ((r = ensure_keys(s))) return r;
+    HIPCHK(s, enqueue_step(s, st));
+    advance_mirror(s, 1);
+    HIPCHK(s, hipEventRecord(ev[0], st));
+    for (int32_t k = 0; k < trial_steps; ++k) HIPCHK(s, enqueue_step(s, st));
+    HIPCHK(s, hipEventRecord(ev[1], st));
+    HIPCHK(s, hipEventSynchronize(ev[1]));
+    advance_mirror(s, trial_steps);
+    float f = 0.f;
+    HIPCHK(s, hipEventElapsedTime(&f, ev[0], ev[1]));
+    *ms = (double)f / trial_steps;
+    return check_sticky(s);
+  };
+  rc = MPC_OK;
+  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) rc = MPC_EHIP;
+  int bestT = T0, bestG = g0, bestY = y0;
+  double best = 1e300;
+  // coordinate search: tile size, then the persistent grid, then the row block
+  const int Ts[] = {0, 8, 12, 16, 24, 32};
+  const int full = s->num_cu * std::max(1, s->occupancy);
+  const int gs[] = {0, s->num_cu * std::max(1, s->occupancy / 2), 2 * full};
+  const int ys[] = {8, 4, 16};
+  for (int T : Ts) {
+    double ms;
+    if (rc || (rc = trial(T, 0, 8, &ms))) break;
+    if (ms < best) best = ms, bestT = T, bestG = 0, bestY = 8;
+  }
+  for (int g : gs) {
+    double ms;
+    if (rc || g == 0) continue;
+    if ((rc = trial(bestT, (g + 7) / 8 * 8, bestY, &ms))) break;
+    if (ms < best) best = ms, bestG = (g + 7) / 8 * 8;
+  }
+  for (int yb : ys) {
+    double ms;
+    if (rc || yb == 8) continue;
+    if ((rc = trial(bestT, bestG, yb, &ms))) break;
+    if (ms < best) best = ms, bestY = yb;
+  }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  const std::string why = s->err;
+  int rc2 = mpc_set_tiling(s, rc ? T0 : bestT, rc ? g0 : bestG, rc ? y0 : bestY);
+  int rc3 = restore();
+  release();
+  if (rc) {
+    s->err = "autotune: " + why;
+    return rc;
+  }
+  if (rc2) return rc2;
+  if (rc3) return rc3;
+  if (tile_cells) *tile_cells = bestT;
+  if (grid) *grid = (int32_t)s->L.collide_grid;
+  return MPC_OK;
 }
 
 }  // extern "C"

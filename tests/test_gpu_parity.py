@@ -232,6 +232,32 @@ def test_graph_and_direct_launches_agree(mpc):
     np.testing.assert_array_equal(res[0][1], res[1][1])
 
 
+def test_autotune_keeps_results(mpc):
+    """The autotuner restores the state and step counter after its trials, and
+    results do not depend on the tiling it picks."""
+    box = box_of((40, 36, 30), mbs=True, seed=31)
+    x, v = synth.box_state(box["L"], seed=32)
+    with mpc.Sim(box, form="fp64", reorder_every=5) as sim:
+        sim.set_state(x, v)
+        sim.step(2)
+        tc, grid = sim.autotune(trial_steps=2)
+        print(f"autotune picked tile_cells={tc} grid={grid}: {sim.get_tiling()}")
+        assert sim.get_step() == 2
+        assert tc in (0, 8, 12, 16, 24, 32) and grid > 0
+        sim.step(4)
+        xa, va = sim.get_state()
+        ka, pa, oa = sim.get_binning()
+    with mpc.Sim(box, form="fp64", reorder_every=5) as sim:
+        sim.set_state(x, v)
+        sim.step(6)
+        xb, vb = sim.get_state()
+        kb, pb, ob = sim.get_binning()
+    np.testing.assert_array_equal(xa, xb)
+    np.testing.assert_array_equal(va, vb)
+    np.testing.assert_array_equal(pa, pb)
+    np.testing.assert_array_equal(oa, ob)
+
+
 def test_deterministic(mpc):
     box = box_of((12, 12, 12), mbs=True, seed=8)
     x, v = synth.box_state(box["L"], seed=4)

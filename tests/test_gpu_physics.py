@@ -1,0 +1,100 @@
+"""GPU runs of the wall-bounded and precision workloads at reduced size.
+
+* Poiseuille flow (walls at z = 0 and z = H, gravity along x, thermostat,
+  split form): the time-averaged profile v_x(z) is the parabola
+  rho g z (H - z) / (2 eta) of a Newtonian fluid between no-slip walls (Sec. II,
+  boundary conditions and external fields).  eta is the SRD viscosity with
+  random grid shift (kinetic + collisional parts) of the method's literature;
+  the check is the parabolic shape, the curvature within 7 % and no slip.
+* Precision form vs FP64 form (plain SRD, which conserves energy): energy and
+  momentum drifts over 100 steps from one initial state.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+DEG = math.pi / 180.0
+
+
+@pytest.fixture(scope="module")
+def mpc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_15236_amd as m
+    m.lib()
+    return m
+
+
+def srd_viscosity(nc, kT, h, alpha, m=1.0, a=1.0):
+    """Shear viscosity of 3D SRD with random shift: kinetic + collisional."""
+    c1, c2 = math.cos(alpha), math.cos(2 * alpha)
+    f = nc - 1 + math.exp(-nc)
+    eta_kin = nc * kT * h / a ** 3 * (5 * nc / (f * (4 - 2 * c1 - 2 * c2)) - 0.5)
+    eta_col = m / (18 * a * h) * f * (1 - c1)
+    return eta_kin + eta_col
+
+
+def test_poiseuille_profile(mpc):
+    # 16 x 16 x 20 cells, g = 5e-3 (Reynolds number ~ 7): the profile's
+    # thermal noise decorrelates on the channel's momentum-diffusion time
+    # H^2 / (pi^2 nu) ~ 470 steps, so the average spans ~13 of them
+    L = (16, 16, 20)
+    H = L[2]
+    g = 5e-3
+    box = dict(L=L, h=0.1, alpha=130 * DEG, kT=1.0, mass=1.0, density=10.0, seed=77,
+               mbs=True, walls=True, g=(g, 0.0, 0.0))
+    x, v = synth.box_state(L, seed=78)
+    nz = H
+    acc = np.zeros(nz)
+    cnt = np.zeros(nz)
+    with mpc.Sim(box, form="split", reorder_every=20) as sim:
+        sim.set_state(x, v)
+        sim.step(3000)
+        for _ in range(300):
+            sim.step(20)
+            xs, vs = sim.get_state()
+            zb = np.clip(np.floor(xs[2]).astype(int), 0, nz - 1)
+            acc += np.bincount(zb, weights=vs[0], minlength=nz)
+            cnt += np.bincount(zb, minlength=nz)
+        o = sim.observables()
+    prof = acc / cnt
+    zc = np.arange(nz) + 0.5
+    # v(z) = A z (H - z) + B: the curvature -2A = -rho g / eta fixes the
+    # viscosity; B is the slip velocity at the walls
+    X = np.stack([zc * (H - zc), np.ones(nz)], axis=1)
+    (A, B), *_ = np.linalg.lstsq(X, prof, rcond=None)
+    resid = prof - X @ np.array([A, B])
+    r2 = 1 - (resid @ resid) / ((prof - prof.mean()) @ (prof - prof.mean()))
+    eta = srd_viscosity(10.0, 1.0, 0.1, 130 * DEG)
+    A_th = 10.0 * g / (2 * eta)
+    print(f"Poiseuille: A = {A:.4e} (theory {A_th:.4e}, ratio {A / A_th:.3f}), slip B = {B:.4f} "
+          f"({B / (A * H * H / 4):.3f} of v_max), R^2 = {r2:.4f}, T = {o['T']:.4f}")
+    assert r2 > 0.98
+    assert abs(A / A_th - 1) < 0.07
+    assert abs(B) < 0.07 * A * H * H / 4
+    assert abs(o["T"] - 1.0) < 0.05
+
+
+def test_precision_form_drift(mpc):
+    L = (64, 64, 64)
+    box = dict(L=L, h=0.1, alpha=130 * DEG, kT=1.0, mass=1.0, density=10.0, seed=5)
+    x, v = synth.box_state(L, seed=6)
+    res = {}
+    for form in ("fp64", "split"):
+        with mpc.Sim(box, form=form, reorder_every=0) as sim:
+            sim.set_state(x, v)
+            o0 = sim.observables()
+            sim.step(100)
+            o1 = sim.observables()
+        res[form] = (o0, o1)
+        dE = abs(o1["E"] - o0["E"]) / o0["E"]
+        dP = np.abs(o1["P"] - o0["P"]).max() / math.sqrt(x.shape[1])
+        print(f"{form}: 100 steps |dE|/E = {dE:.3e}, max |dP| / sqrt(N) = {dP:.3e}")
+        res[form] += (dE, dP)
+    assert res["fp64"][2] < 1e-12 and res["fp64"][3] < 1e-12
+    assert res["split"][2] < 1e-5 and res["split"][3] < 1e-5
