@@ -27,6 +27,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -84,6 +86,101 @@ def run_box(mpc, torch, box: dict, form: str, R: int, steps: int, warmup: int,
     return n, wall, kt, obs
 
 
+def srd_viscosity(nc, kT, h, alpha, m=1.0, a=1.0):
+    """Shear viscosity of 3D SRD with random grid shift (kinetic + collisional)."""
+    c1, c2 = math.cos(alpha), math.cos(2 * alpha)
+    f = nc - 1 + math.exp(-nc)
+    return (nc * kT * h / a ** 3 * (5 * nc / (f * (4 - 2 * c1 - 2 * c2)) - 0.5)
+            + m / (18 * a * h) * f * (1 - c1))
+
+
+def run_c3(mpc, torch, synth, steps: int):
+    """512^3 plain SRD, FP64 and split from the same device-initialised state
+    (seed 3): throughput and energy / momentum drift of each form."""
+    box = synth.config("C3")
+    out = {"workload": "512^3 periodic cells, 10/cell (1,342,177,280 particles), plain SRD, "
+                       f"kT=1, h=0.1, alpha=130deg, same initial state, {steps} steps"}
+    for form in ("fp64", "split"):
+        sim = mpc.Sim(box, form=form, reorder_every=0, graph=True)
+        sim.init_state(3)
+        o0 = sim.observables()
+        n = o0["N"]
+        sim.step(2)
+        sim.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.sync()
+        wall = time.perf_counter() - t0
+        o1 = sim.observables()
+        out[form] = {"value": n * steps / wall, "unit": "particle-steps/s",
+                     "ms_per_step": wall * 1e3 / steps,
+                     "energy_drift_rel": abs(o1["E"] - o0["E"]) / o0["E"],
+                     "momentum_drift_per_sqrtN": float(np.abs(o1["P"] - o0["P"]).max()
+                                                       / math.sqrt(n)),
+                     "T_end": o1["T"]}
+        print(f"[C3 {form}] {wall * 1e3 / steps:.2f} ms/step, dE/E {out[form]['energy_drift_rel']:.3e}",
+              file=sys.stderr, flush=True)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    out["T_diff_split_vs_fp64"] = out["split"]["T_end"] - out["fp64"]["T_end"]
+    return out
+
+
+def run_c5(mpc, torch, synth, steps: int):
+    """Poiseuille flow, 256 x 256 x 64 cells between no-slip walls, gravity
+    1e-3 along x, thermostat, split form: throughput and the time-averaged
+    profile v_x(z) against the parabola rho g z (H - z) / (2 eta)."""
+    box = synth.config("C5")
+    L = box["L"]
+    H = L[2]
+    sim = mpc.Sim(box, form="split", reorder_every=20, graph=True)
+    sim.init_state(5)
+    n = sim.n()
+    nsnap, gap = 10, 200
+    run = steps - nsnap * gap
+    sim.step(2)
+    sim.sync()
+    t0 = time.perf_counter()
+    done = 0
+    while done < run - 2:
+        k = min(2000, run - 2 - done)
+        sim.step(k)
+        sim.sync()
+        done += k
+        print(f"[C5] {done + 2} steps", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    acc = np.zeros(H)
+    cnt = np.zeros(H)
+    for _ in range(nsnap):
+        sim.step(gap)
+        x, v = sim.get_state()
+        zb = np.clip(np.floor(x[2]).astype(np.int64), 0, H - 1)
+        acc += np.bincount(zb, weights=v[0], minlength=H)
+        cnt += np.bincount(zb, minlength=H)
+        del x, v
+    o = sim.observables()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    prof = acc / cnt
+    zc = np.arange(H) + 0.5
+    X = np.stack([zc * (H - zc), np.ones(H)], axis=1)
+    (A, B), *_ = np.linalg.lstsq(X, prof, rcond=None)
+    resid = prof - X @ np.array([A, B])
+    r2 = 1 - float(resid @ resid) / float((prof - prof.mean()) @ (prof - prof.mean()))
+    eta = srd_viscosity(box["density"], box["kT"], box["h"], box["alpha"])
+    A_th = box["density"] * box["g"][0] / (2 * eta)
+    return {"workload": "256x256x64 cells between no-slip walls, 10/cell (41,943,040 particles), "
+                        "g=1e-3 along x, MBS, split form, " + f"{steps} steps",
+            "value": n * (run - 2) / wall, "unit": "particle-steps/s",
+            "ms_per_step": wall * 1e3 / (run - 2),
+            "profile_curvature_vs_theory": A / A_th, "slip_over_vmax": B / (A * H * H / 4),
+            "profile_r2": r2, "v_max": A * H * H / 4 + B, "T_end": o["T"],
+            "eta_theory": eta, "profile": [round(float(q), 5) for q in prof]}
+
+
 def cpu_baseline(seconds_hint: float = 15.0):
     """Single-threaded FP64 oracle on a 128^3 sample of the 256^3 workload."""
     import oracle
@@ -121,6 +218,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=500)
     ap.add_argument("--reorder-every", type=int, default=20)
+    ap.add_argument("--c3-steps", type=int, default=100)
+    ap.add_argument("--c5-steps", type=int, default=20000)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -213,6 +312,10 @@ def main():
                     "collide_achieved_GBs": n2 * 2 * STATE_BYTES["fp64"] / (c2 * 1e-3) / 1e9}
                 print(f"[fp64 R=1 C2] {w2 * 1e3 / args.steps:.3f} ms/step collide {c2:.3f} ms",
                       file=sys.stderr)
+            elif form == "c3":
+                forms["c3"] = run_c3(mpc, torch, synth, args.c3_steps)
+            elif form == "c5":
+                forms["c5"] = run_c5(mpc, torch, synth, args.c5_steps)
             elif form == "batched":
                 boxes = synth.batch_boxes(64, seed=4)
                 nb, wb, _, _ = run_box(mpc, torch, boxes, "fp64", 0, args.batched_steps,
