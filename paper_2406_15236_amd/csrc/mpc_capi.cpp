@@ -36,7 +36,7 @@ struct Plan {
   bool split = false;
   // byte offsets in the workspace
   size_t off_S[2][8] = {};
-  bool ids = false;  // logical-index arrays (reorder interval other than 1)
+  bool ids = true;  // logical-index arrays (the stored order is free)
   size_t off_key = 0, off_perm = 0, off_hist = 0, off_offset = 0, off_scan = 0, off_ctrl = 0,
          off_boxes = 0, off_tiles = 0, off_pblocks = 0, off_partials = 0, off_vmean = 0,
          off_draws = 0;
@@ -118,7 +118,7 @@ int make_plan(const mpc_params* p, int32_t nbox, Plan& P, std::string* why) {
   }
   const int form = p[0].form;
   P.split = form == MPC_SPLIT32;
-  P.ids = p[0].reorder_every != 1;
+  P.ids = true;
   P.state_elem_a = form == MPC_FP64 ? 8 : 4;
   P.state_elem_b = form == MPC_FP64 ? 8 : 4;
   size_t off = 0;
@@ -205,11 +205,12 @@ int hip_fail(mpc_sim* s, hipError_t e, const char* where) {
     if (_e != hipSuccess) return hip_fail((s), _e, #expr); \
   } while (0)
 
+// Cells per tile so that a tile's mean particle count is ~95 % of the LDS
+// capacity of one pass (larger tiles amortise the per-tile work; the Poisson
+// excess of a full tile goes to a second pass).
 int auto_tile_cells(double density) {
-  const double target = 0.65 * kTileCap / density;
-  int t = kTileMaxCells;
-  while (t > kMinTileCells && (double)t > target) t >>= 1;
-  return t;
+  const double target = 0.95 * kTileCap / density;
+  return (int)std::max<double>(kMinTileCells, std::min<double>(kTileMaxCells, floor(target)));
 }
 
 // Tiles are runs of at most T consecutive cells inside one row (fixed y and z),

@@ -71,10 +71,11 @@ struct CellDraw {       // random draws of one cell for the current step
 
 // State buffers of one form, SoA.  F64: a[0..2]=x (double), b[0..2]=v (double);
 // F32: x, v float; Split: cell (u32), a = offsets (float), b = v (float).
-// Every step writes the state in cell order into the other buffer.  `id` holds
-// each stored particle's logical index (its index in the caller's order, which
-// is renumbered to the stored order only on reorder steps); it is null when
-// every step is a reorder step (R = 1): the logical index is then the slot.
+// Every step writes the state into the other buffer, cell by cell of the
+// current step, and inside the particles of one tile pass grouped by their
+// cell of the next step (so that the next step gathers contiguous runs).
+// `id` holds each stored particle's logical index: its index in the caller's
+// order, renumbered to the (cell, index) order on reorder steps.
 struct StatePtrs {
   void* a[3];
   void* b[3];

@@ -859,6 +859,27 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict
 // ---------------------------------------------------------------------------
 // Collide (+ stream/bin of the next step)
 // ---------------------------------------------------------------------------
+// Entry of next-step cell c in the window of the tile whose first cell is
+// (x0, y0, z0): row r = (dz + 1) * 3 + (dy + 1) for the rows y0 + dy, z0 + dz
+// (dy, dz in {-1, 0, 1}; periodic axes taken modulo L), column
+// dx = (c_x - x0 + 1) mod L0 < WX = cells of the tile + 2.  False when the
+// cell lies outside the window (the particle moved more than one cell).
+template <bool W>
+__device__ __forceinline__ bool win_entry(const int (&c)[3], int x0, int y0, int z0, int WX,
+                                          int L0, int L1, int L2, int& r, int& dx) {
+  dx = wrap1(c[0] - x0 + 1, L0);
+  int dy = c[1] - y0;
+  dy += L1 & -(int)(dy < -1);
+  dy -= L1 & -(int)(dy > 1);
+  int dz = c[2] - z0;
+  if (!W) {
+    dz += L2 & -(int)(dz < -1);
+    dz -= L2 & -(int)(dz > 1);
+  }
+  r = (dz + 1) * 3 + (dy + 1);
+  return (unsigned)dx < (unsigned)WX && (unsigned)(dy + 1) < 3u && (unsigned)(dz + 1) < 3u;
+}
+
 // Number of entries of seg[b..e) smaller than i (four independent LDS reads
 // per trip so that they overlap).
 __device__ __forceinline__ uint32_t rank_in_segment(const uint32_t* seg, uint32_t b, uint32_t e,
@@ -1050,9 +1071,11 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   __shared__ uint32_t s_c[Fm::kHasCell ? kTileCap : 1];
   __shared__ CellLds s_cell[kTileMaxCells];
   __shared__ double s_sh[6];
-  // next-step histogram of the tile: cells x0-1 .. x0+nc of rows (y0+-1, z0+-1)
-  constexpr int kWin = 9 * (kTileMaxCells + 2);
-  __shared__ uint32_t s_hw[kWin];
+  // next-step window of the tile: cells x0-1 .. x0+nc of the rows (y0 +- 1,
+  // z0 +- 1), plus one entry for particles that leave it; per pass: counts,
+  // then their exclusive prefix (the output order of the pass)
+  constexpr int kWin = 9 * (kTileMaxCells + 2) + 1;
+  __shared__ uint32_t s_pc[kWin];
 
   const uint64_t t = as_const(d.ctrl)->step;
   const uint32_t cur = as_const(d.ctrl)->cur;
@@ -1123,7 +1146,6 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
     const int z0 = (int)(lkey0 / (uint32_t)(B.L[0] * B.L[1]));
     const int WX = (int)T.nc + 2;
     const int L0 = B.L[0], L1 = B.L[1], L2 = B.L[2];
-    for (int i = lane; i < 9 * WX; i += NT) s_hw[i] = 0u;
     // offsets of the tile after next (two ahead)
     uint32_t off_after = 0;
     if (tafter != 0xffffffffu) {
@@ -1276,7 +1298,10 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
       }
       wave_sync();
 
-      // Phase D: rotate + scale, gravity, write, stream + bin step t+1
+      // Phase D1: rotate + scale, gravity; the next step's cell of each
+      // particle and its rank among the pass's particles going there
+      for (int i = (int)lane; i < 9 * WX + 1; i += NT) s_pc[i] = 0u;
+      wave_sync();
       const double snext[3] = {s_sh[3], s_sh[4], s_sh[5]};
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
@@ -1321,66 +1346,85 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) v.v[a] = (Vs)w[a];
           }
-          const uint32_t j = base + q;
-          if (j < d.ntot) {
+          // v' back in place; the next step's cell and its window entry
+          s_v[0][q] = v.v[0];
+          s_v[1][q] = v.v[1];
+          s_v[2][q] = v.v[2];
+          Fm::template stream<W>(p, v, B);
+          int c[3];
+          Fm::template coords<W>(p, snext, B, c, err);
+          const uint32_t kn = B.cbase + linear_key(c, B);
+          int r, dx;
+          uint32_t e = (uint32_t)(9 * WX);
+          if (win_entry<W>(c, x0, y0, z0, WX, L0, L1, L2, r, dx)) {
+            e = (uint32_t)(r * WX + dx);
+          } else {
+            atomicAdd(&d.hist[kn], 1u);
+          }
+          const uint32_t rank = atomicAdd(&s_pc[e], 1u);
+          s_idx[q] = e << 16 | rank;
+          s_rk[q] = kn;
+        }
+      }
+      wave_sync();
+      // exclusive prefix of the pass's window counts (5 entries per lane)
+      {
+        const int ne = 9 * WX + 1;
+        const int i0 = (int)lane * 5;
+        uint32_t cnt5[5];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+          cnt5[m] = i0 + m < ne ? s_pc[i0 + m] : 0u;
+          sum += cnt5[m];
+        }
+        const uint32_t incl = wave_inclusive_scan(sum);
+        uint32_t run = incl - sum;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+          if (i0 + m < ne) s_pc[i0 + m] = run;
+          run += cnt5[m];
+        }
+      }
+      wave_sync();
+      // D2: the pass's particles, grouped by next-step cell, into its slots;
+      // logical indices: the canonical (cell, index) position on reorder steps
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const uint32_t q = lane + k * NT;
+        __builtin_amdgcn_sched_barrier(0);
+        if (q < np) {
+          const uint32_t pk = s_idx[q];
+          const uint32_t j = base + s_pc[pk >> 16] + (pk & 0xffffu);
+          if (j < d.ntot && j < base + np) {
+            typename Fm::P p;
+            typename Fm::Vv v;
+            Fm::from_lds(p, s_x[0], s_x[1], s_x[2], s_c, q);
+            v.v[0] = s_v[0][q];
+            v.v[1] = s_v[1][q];
+            v.v[2] = s_v[2][q];
             Fm::store(out, j, p, v);
-            if (track) out.id[j] = renumber ? j : s_idc[q];
-            Fm::template stream<W>(p, v, B);
-            int c[3];
-            Fm::template coords<W>(p, snext, B, c, err);
-            const uint32_t kn = B.cbase + linear_key(c, B);
-            d.key[j] = kn;
-            const int dx = wrap1(c[0] - x0 + 1, L0);
-            int dy = c[1] - y0;
-            dy += L1 & -(int)(dy < -1);
-            dy -= L1 & -(int)(dy > 1);
-            int dz = c[2] - z0;
-            if (!W) {
-              dz += L2 & -(int)(dz < -1);
-              dz -= L2 & -(int)(dz > 1);
-            }
-            if ((unsigned)dx < (unsigned)WX && (unsigned)(dy + 1) < 3u &&
-                (unsigned)(dz + 1) < 3u) {
-              atomicAdd(&s_hw[((dz + 1) * 3 + (dy + 1)) * WX + dx], 1u);
-            } else {
-              atomicAdd(&d.hist[kn], 1u);
-            }
+            if (track) out.id[j] = renumber ? base + q : s_idc[q];
+            d.key[j] = s_rk[q];
           } else {
             err |= kErrKey;
           }
         }
       }
-      cs = ce;
-      wave_sync();
-    }
-    // flush the tile's window into the global histogram
-#pragma unroll
-    for (int r = 0; r < 9; ++r) {
-      const int dzi = r / 3, dyi = r % 3;
-      for (int dx = lane; dx < WX; dx += NT) {
-        const uint32_t cnt = s_hw[r * WX + dx];
+      // this pass's window counts into the global histogram
+      for (int i = (int)lane; i < 9 * WX; i += NT) {
+        const uint32_t cnt = s_pc[i + 1] - s_pc[i];
         if (cnt) {
-          int c[3] = {x0 - 1 + dx, y0 + dyi - 1, z0 + dzi - 1};
-          if (c[0] < 0) {
-            c[0] += B.L[0];
-          } else if (c[0] >= B.L[0]) {
-            c[0] -= B.L[0];
-          }
-          if (c[1] < 0) {
-            c[1] += B.L[1];
-          } else if (c[1] >= B.L[1]) {
-            c[1] -= B.L[1];
-          }
-          if (!W) {
-            if (c[2] < 0) {
-              c[2] += B.L[2];
-            } else if (c[2] >= B.L[2]) {
-              c[2] -= B.L[2];
-            }
-          }
+          const int rr = i / WX, dx = i - rr * WX;
+          int c[3] = {x0 - 1 + dx, y0 + rr % 3 - 1, z0 + rr / 3 - 1};
+          c[0] = wrap1(c[0], L0);
+          c[1] = wrap1(c[1], L1);
+          if (!W) c[2] = wrap1(c[2], L2);
           atomicAdd(&d.hist[B.cbase + linear_key(c, B)], cnt);
         }
       }
+      cs = ce;
+      wave_sync();
     }
     // advance the pipeline
     tcur = tnext;
