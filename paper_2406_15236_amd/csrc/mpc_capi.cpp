@@ -37,6 +37,7 @@ struct Plan {
   // byte offsets in the workspace
   size_t off_S[2][8] = {};
   bool ids = true;  // logical-index arrays (the stored order is free)
+  size_t off_rank = 0;
   size_t off_key = 0, off_perm = 0, off_hist = 0, off_offset = 0, off_scan = 0, off_ctrl = 0,
          off_boxes = 0, off_tiles = 0, off_pblocks = 0, off_partials = 0, off_vmean = 0,
          off_draws = 0;
@@ -135,6 +136,7 @@ int make_plan(const mpc_params* p, int32_t nbox, Plan& P, std::string* why) {
   }
   P.off_key = take(4 * P.ntot);
   P.off_perm = take(4 * P.ntot);
+  P.off_rank = take(2 * P.ntot);
   P.off_hist = take(4 * P.cpad);
   P.off_offset = take(4 * (P.cpad + 1));
   P.off_scan = take(4 * (size_t)P.nscan);
@@ -447,6 +449,7 @@ int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
   }
   s->dev.key = (uint32_t*)(ws + P.off_key);
   s->dev.perm = (uint32_t*)(ws + P.off_perm);
+  s->dev.rank = (uint16_t*)(ws + P.off_rank);
   s->dev.hist = (uint32_t*)(ws + P.off_hist);
   s->dev.offset = (uint32_t*)(ws + P.off_offset);
   s->dev.scan_blk = (uint32_t*)(ws + P.off_scan);
@@ -532,6 +535,7 @@ int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
       launch_zero_u32(s->dev.hist, P.cpad, s->L.stream) != hipSuccess ||
       launch_zero_u32(s->dev.perm, P.ntot, s->L.stream) != hipSuccess ||
       launch_zero_u32(s->dev.key, P.ntot, s->L.stream) != hipSuccess ||
+      launch_zero_u32((uint32_t*)s->dev.rank, (P.ntot + 1) / 2, s->L.stream) != hipSuccess ||
       launch_zero_u32(s->dev.offset, P.cpad + 1, s->L.stream) != hipSuccess ||
       launch_set_ctrl(s->dev, s->L, 0, 0, s->R, 1) != hipSuccess ||
       hipStreamSynchronize(s->L.stream) != hipSuccess)

@@ -1,18 +1,19 @@
 // mpc_kernels.hip -- gfx950 kernels of the MPC-SRD step (arXiv:2406.15236, Sec. II).
 //
 // One step t on the device (steady state):
-//   scan    : offset = exclusive prefix of hist (particles per cell of step t)
-//   scatter : slot = offset[key] + atomicSub(hist[key]) - 1; perm[slot] = i
-//             (leaves hist at zero)
+//   scan    : offset = exclusive prefix of hist (particles per cell of step t),
+//             per-cell random draws; hist is zeroed for the next count
+//   scatter : perm[offset[key] + rank] = i (each particle already holds its
+//             rank inside its cell)
 //   collide : per tile of cells: gather the cell segments through perm, order
-//             each segment by storage index in LDS, stream (Eq. 1), sum the
-//             cells one thread per cell, draw axis / thermostat from Philox,
-//             rotate (Eq. 2) + scale, write the state (in place, or in cell
-//             order into the other buffer on reorder steps), and already
-//             stream + bin for step t+1: key[] and hist[] of the next step.
-//   advance : t += 1, flip the buffer after a reorder step.
-// The prologue kernel computes key/hist of step t when the state was set from
-// outside.  Every kernel reads the step index and buffer from Ctrl, so a
+//             each segment by logical index in LDS, stream (Eq. 1), sum the
+//             cells one thread per cell, rotate (Eq. 2) + scale with the draws,
+//             stream + bin for step t+1, and write the state into the other
+//             buffer, each tile pass grouped by next-step cell; the next
+//             step's counts and ranks come from one atomic per (pass, cell).
+//   advance : t += 1, flip the buffers.
+// The prologue kernel computes key/hist/rank of step t when the state was set
+// from outside.  Every kernel reads the step index and buffer from Ctrl, so a
 // captured graph of one step can be replayed.
 #include <math.h>
 
@@ -598,6 +599,29 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* hist, uint32_t c, bool a
   if (active && (mine & lt_mask) == 0ull) atomicAdd(&hist[c], (uint32_t)__popcll(mine));
 }
 
+// hist[c] += 1 for every active lane, one atomic per distinct key in the
+// wavefront; returns the lane's rank among all particles counted for c (the
+// old count of its run's leader plus its place in the run).
+__device__ __forceinline__ uint32_t wave_hist_rank(uint32_t* hist, uint32_t c, bool active) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint64_t pending = __ballot(active);
+  uint64_t mine = 0;
+  while (pending) {
+    const int lead = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t lc = (uint32_t)__builtin_amdgcn_readlane((int)c, lead);
+    const uint64_t same = __ballot(active && c == lc) & pending;
+    if (active && c == lc) mine = same;
+    pending &= ~same;
+  }
+  const uint32_t before = (uint32_t)__popcll(mine & lt_mask);
+  uint32_t old = 0;
+  if (active && before == 0) old = atomicAdd(&hist[c], (uint32_t)__popcll(mine));
+  const int lead_lane = active ? (__ffsll((unsigned long long)mine) - 1) : (int)lane;
+  old = __shfl(old, lead_lane, 64);
+  return old + before;
+}
+
 // Prologue: key and histogram of step t from the current state.
 template <int F, bool W>
 __global__ __launch_bounds__(kThreads) void k_key_hist(Dev d) {
@@ -630,7 +654,8 @@ __global__ __launch_bounds__(kThreads) void k_key_hist(Dev d) {
       key = B.cbase + Fm::template key<W>(p, s, B, err);
       d.key[i] = key;
     }
-    wave_hist_add(d.hist, key, i < pend);
+    const uint32_t rk = wave_hist_rank(d.hist, key, i < pend);
+    if (i < pend) d.rank[i] = (uint16_t)min(rk, 0xffffu);
   }
   if (err) atomicOr(&d.ctrl->err, err);
 }
@@ -742,7 +767,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(Dev d, uint32_t nblk, ui
                                                         uint32_t ctot) {
   __shared__ uint32_t s_w[kThreads / 64];
   const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanItems;
-  const uint4* h4 = (const uint4*)(d.hist + base);
+  uint4* h4 = (uint4*)(d.hist + base);
   uint32_t v[kScanItems];
 #pragma unroll
   for (int k = 0; k < kScanItems / 4; ++k) {
@@ -751,6 +776,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(Dev d, uint32_t nblk, ui
     v[4 * k + 1] = q.y;
     v[4 * k + 2] = q.z;
     v[4 * k + 3] = q.w;
+    h4[k] = make_uint4(0u, 0u, 0u, 0u);  // the next collide counts from zero
   }
   uint32_t sum = 0;
 #pragma unroll
@@ -809,48 +835,27 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(Dev d, uint32_t nblk, ui
 // segment is arbitrary here and made canonical in collide).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict__ key,
-                                                      uint32_t* __restrict__ hist,
+                                                      const uint16_t* __restrict__ rank,
                                                       const uint32_t* __restrict__ offset,
                                                       uint32_t* __restrict__ perm, uint32_t n,
                                                       uint32_t ncell, Ctrl* ctrl) {
-  // Lanes of a wavefront that carry the same key take their slots with one
-  // atomic of the run's leader (lowest lane); the others are ranked after it.
-  const uint32_t lane = threadIdx.x & 63;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // Every particle already holds its rank among the particles of its cell
+  // (taken when the cell's count was accumulated): no atomics here.
   uint32_t bad = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const uint32_t i = blockIdx.x * (kThreads * 4) + k * kThreads + threadIdx.x;
-    uint32_t c = i < n ? key[i] : 0xffffffffu;
-    if (i < n && c >= ncell) {
+    if (i >= n) continue;
+    const uint32_t c = key[i];
+    if (c >= ncell) {
       bad = 1;
-      c = 0xffffffffu;
+      continue;
     }
-    // group equal keys: find the leader (lowest lane) of each key
-    uint64_t pending = __ballot(c != 0xffffffffu);
-    uint64_t my_group = 0;
-    while (pending) {
-      const int lead = __ffsll((unsigned long long)pending) - 1;
-      const uint32_t lc = (uint32_t)__builtin_amdgcn_readlane((int)c, lead);
-      const uint64_t same = __ballot(c == lc) & pending;
-      if (c == lc && ((pending >> lane) & 1ull)) my_group = same;
-      pending &= ~same;
-    }
-    const bool valid = c != 0xffffffffu;
-    const uint32_t cnt = valid ? (uint32_t)__popcll(my_group) : 0u;
-    const uint32_t rank = valid ? (uint32_t)__popcll(my_group & lt_mask) : 0u;
-    const bool leader = valid && rank == 0;
-    uint32_t old = 0;
-    if (leader) old = atomicSub(&hist[c], cnt);
-    const int lead_lane = valid ? (__ffsll((unsigned long long)my_group) - 1) : (int)lane;
-    old = __shfl(old, lead_lane, 64);
-    if (valid) {
-      const uint32_t slot = offset[c] + old - 1u - rank;
-      if (old < cnt || slot >= n) {
-        bad = 1;
-      } else {
-        perm[slot] = i;
-      }
+    const uint32_t slot = offset[c] + rank[i];
+    if (slot >= offset[c + 1] || slot >= n) {
+      bad = 1;
+    } else {
+      perm[slot] = i;
     }
   }
   if (bad) atomicOr(&ctrl->err, kErrKey);
@@ -1205,7 +1210,8 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             kn = B.cbase + Fm::template key<W>(p, snx, B, err);
             d.key[j] = kn;
           }
-          wave_hist_add(d.hist, kn, live);
+          const uint32_t rk = wave_hist_rank(d.hist, kn, live);
+          if (live) d.rank[base + q] = (uint16_t)min(rk, 0xffffu);
         }
         cs = ce;
         wave_sync();
@@ -1355,19 +1361,20 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
           Fm::template coords<W>(p, snext, B, c, err);
           const uint32_t kn = B.cbase + linear_key(c, B);
           int r, dx;
-          uint32_t e = (uint32_t)(9 * WX);
-          if (win_entry<W>(c, x0, y0, z0, WX, L0, L1, L2, r, dx)) {
-            e = (uint32_t)(r * WX + dx);
-          } else {
-            atomicAdd(&d.hist[kn], 1u);
-          }
+          uint32_t e = (uint32_t)(9 * WX);  // outside the window: counted in D2
+          if (win_entry<W>(c, x0, y0, z0, WX, L0, L1, L2, r, dx)) e = (uint32_t)(r * WX + dx);
           const uint32_t rank = atomicAdd(&s_pc[e], 1u);
           s_idx[q] = e << 16 | rank;
           s_rk[q] = kn;
         }
       }
       wave_sync();
-      // exclusive prefix of the pass's window counts (5 entries per lane)
+      // Per window entry (5 per lane): add the pass's count to the next
+      // step's histogram, whose old value is the rank base of these particles
+      // in their cell (used after D2, so that the atomics' latency overlaps
+      // the stores); and the exclusive prefix of the counts, which orders the
+      // pass's output.
+      uint32_t rb5[5];
       {
         const int ne = 9 * WX + 1;
         const int i0 = (int)lane * 5;
@@ -1375,8 +1382,18 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
         uint32_t sum = 0;
 #pragma unroll
         for (int m = 0; m < 5; ++m) {
-          cnt5[m] = i0 + m < ne ? s_pc[i0 + m] : 0u;
+          const int i = i0 + m;
+          cnt5[m] = i < ne ? s_pc[i] : 0u;
           sum += cnt5[m];
+          rb5[m] = 0u;
+          if (i < ne - 1 && cnt5[m]) {
+            const int rr = i / WX, dx = i - rr * WX;
+            int c[3] = {x0 - 1 + dx, y0 + rr % 3 - 1, z0 + rr / 3 - 1};
+            c[0] = wrap1(c[0], L0);
+            c[1] = wrap1(c[1], L1);
+            if (!W) c[2] = wrap1(c[2], L2);
+            rb5[m] = atomicAdd(&d.hist[B.cbase + linear_key(c, B)], cnt5[m]);
+          }
         }
         const uint32_t incl = wave_inclusive_scan(sum);
         uint32_t run = incl - sum;
@@ -1396,6 +1413,8 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
         if (q < np) {
           const uint32_t pk = s_idx[q];
           const uint32_t j = base + s_pc[pk >> 16] + (pk & 0xffffu);
+          const uint32_t kn = s_rk[q];
+          s_rk[q] = j;
           if (j < d.ntot && j < base + np) {
             typename Fm::P p;
             typename Fm::Vv v;
@@ -1405,22 +1424,38 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             v.v[2] = s_v[2][q];
             Fm::store(out, j, p, v);
             if (track) out.id[j] = renumber ? base + q : s_idc[q];
-            d.key[j] = s_rk[q];
+            d.key[j] = kn;
+            // leaving the window: counted one by one
+            if ((pk >> 16) == (uint32_t)(9 * WX))
+              d.rank[j] = (uint16_t)min(atomicAdd(&d.hist[kn], 1u), 0xffffu);
           } else {
             err |= kErrKey;
           }
         }
       }
-      // this pass's window counts into the global histogram
-      for (int i = (int)lane; i < 9 * WX; i += NT) {
-        const uint32_t cnt = s_pc[i + 1] - s_pc[i];
-        if (cnt) {
-          const int rr = i / WX, dx = i - rr * WX;
-          int c[3] = {x0 - 1 + dx, y0 + rr % 3 - 1, z0 + rr / 3 - 1};
-          c[0] = wrap1(c[0], L0);
-          c[1] = wrap1(c[1], L1);
-          if (!W) c[2] = wrap1(c[2], L2);
-          atomicAdd(&d.hist[B.cbase + linear_key(c, B)], cnt);
+      // D3: ranks inside the next-step cells (rank base of the entry + place)
+      wave_sync();
+      {
+        const int ne = 9 * WX + 1;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+          const int i = (int)lane * 5 + m;
+          if (rb5[m] > 0xffffu) {
+            err |= kErrCellOverflow;
+            rb5[m] = 0xffffu;
+          }
+          if (i < ne) s_pc[i] = rb5[m];
+        }
+      }
+      wave_sync();
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const uint32_t q = lane + k * NT;
+        if (q < np) {
+          const uint32_t pk = s_idx[q];
+          const uint32_t j = s_rk[q];
+          if ((pk >> 16) != (uint32_t)(9 * WX) && j < d.ntot && j < base + np)
+            d.rank[j] = (uint16_t)min(s_pc[pk >> 16] + (pk & 0xffffu), 0xffffu);
         }
       }
       cs = ce;
@@ -1707,7 +1742,7 @@ hipError_t launch_scan(const Dev& d, const Launch& l) {
 hipError_t launch_scatter(const Dev& d, const Launch& l) {
   if (l.ntot == 0) return hipSuccess;
   const uint32_t blocks = (uint32_t)((l.ntot + kThreads * 4 - 1) / (kThreads * 4));
-  hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(kThreads), 0, l.stream, d.key, d.hist,
+  hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(kThreads), 0, l.stream, d.key, d.rank,
                      d.offset, d.perm, (uint32_t)l.ntot, (uint32_t)l.ctot, d.ctrl);
   return hipGetLastError();
 }
