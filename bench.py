@@ -61,11 +61,17 @@ def traffic_record(form: str, workload: str, R: int):
 
 
 def run_box(mpc, torch, box: dict, form: str, R: int, steps: int, warmup: int,
-            profiled: bool = True):
+            profiled: bool = True, tune: bool = True):
     sim = mpc.Sim(box if isinstance(box, list) else [box], form=form, reorder_every=R,
                   graph=not profiled)
     sim.init_state(2024)
     n = sum(sim.n(b) for b in range(len(sim.params)))
+    tiling = None
+    if tune:  # the library's autotuner picks the collide tiling (state restored after)
+        sim.step(2)
+        sim.autotune(3)
+        tiling = sim.get_tiling()
+        print(f"  autotuned {form}: {tiling}", file=sys.stderr, flush=True)
     if warmup:
         sim.step(warmup) if not profiled else sim.step_profiled(warmup)
     sim.sync()
@@ -83,6 +89,7 @@ def run_box(mpc, torch, box: dict, form: str, R: int, steps: int, warmup: int,
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    run_box.last_tiling = tiling
     return n, wall, kt, obs
 
 
@@ -279,6 +286,7 @@ def main():
                      "traffic": tr["bytes_per_launch"] if tr else None,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": coll_ms},
+        "launch": {"collide_tiling": run_box.last_tiling, "autotuned": True},
         "kernels_ms_per_step": {"scan": kt.scan_ms / args.steps,
                                 "scatter": kt.scatter_ms / args.steps,
                                 "collide": coll_ms, "advance": kt.other_ms / args.steps},

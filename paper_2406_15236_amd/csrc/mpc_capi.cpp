@@ -1015,8 +1015,11 @@ int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* 
   double best = 1e300;
   // coordinate search: tile size, then the persistent grid, then the row block
   const int Ts[] = {0, 8, 12, 16, 24, 32};
+  // grids: the resident maximum (0), fixed workgroups per CU (fewer waves
+  // in flight per XCD can keep the gathered rows in L2), and oversubscribed
+  // grids (freed slots take the remaining workgroups: better tail balance)
   const int full = s->num_cu * std::max(1, s->occupancy);
-  const int gs[] = {0, s->num_cu * std::max(1, s->occupancy / 2), 2 * full};
+  const int gs[] = {0, 6 * s->num_cu, 8 * s->num_cu, 10 * s->num_cu, 2 * full, 16 * s->num_cu};
   const int ys[] = {8, 4, 16};
   for (int T : Ts) {
     double ms;
