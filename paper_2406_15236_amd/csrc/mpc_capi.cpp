@@ -37,7 +37,7 @@ struct Plan {
   // byte offsets in the workspace
   size_t off_S[2][8] = {};
   bool ids = true;  // logical-index arrays (the stored order is free)
-  size_t off_rank = 0;
+  size_t off_rank = 0, off_phs = 0;
   size_t off_key = 0, off_perm = 0, off_hist = 0, off_offset = 0, off_scan = 0, off_ctrl = 0,
          off_boxes = 0, off_tiles = 0, off_pblocks = 0, off_partials = 0, off_vmean = 0,
          off_draws = 0;
@@ -147,6 +147,7 @@ int make_plan(const mpc_params* p, int32_t nbox, Plan& P, std::string* why) {
   P.off_partials = take(sizeof(double) * 4 * P.npblocks);
   P.off_vmean = take(sizeof(double) * 3 * nbox);
   P.off_draws = take(sizeof(CellDraw) * P.cpad);
+  P.off_phs = (p[0].flags & MPC_WALLS_Z) ? take(sizeof(PhantomSums) * P.cpad) : 0;
   P.total = off;
   return MPC_OK;
 }
@@ -295,6 +296,7 @@ hipError_t enqueue_step(mpc_sim* s, hipStream_t st) {
   l.stream = st;
   hipError_t e;
   if ((e = launch_scan(s->dev, l)) != hipSuccess) return e;
+  if ((e = launch_phantoms(s->dev, l)) != hipSuccess) return e;
   if ((e = launch_scatter(s->dev, l)) != hipSuccess) return e;
   if ((e = launch_collide(s->dev, l)) != hipSuccess) return e;
   return launch_advance(s->dev, l);
@@ -461,9 +463,10 @@ int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
   s->dev.ntot = (uint32_t)P.ntot;
   s->vmean = (double*)(ws + P.off_vmean);
   s->dev.draws = (CellDraw*)(ws + P.off_draws);
+  s->dev.phs = (p[0].flags & MPC_WALLS_Z) ? (PhantomSums*)(ws + P.off_phs) : nullptr;
 
   // boxes
-  uint64_t pb = 0, cb = 0;
+  uint64_t pb = 0, cb = 0, wcb = 0;
   s->box_pb0.push_back(0);
   for (int32_t b = 0; b < nbox; ++b) {
     const mpc_params& q = p[b];
@@ -493,6 +496,8 @@ int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
     B.density = q.density;
     B.sd = sqrt(B.kT / q.mass);
     B.grav = (q.g[0] != 0.0 || q.g[1] != 0.0 || q.g[2] != 0.0) ? 1u : 0u;
+    B.wcbase = (uint32_t)wcb;
+    if (B.walls) wcb += 2ull * (uint64_t)q.L[0] * (uint64_t)q.L[1];
     for (int k = 0; k < 3; ++k) B.gh[k] = (q.g[k] / q.a) * q.dt;
     s->boxes.push_back(B);
     for (uint64_t p0 = 0; p0 < P.box[b].n; p0 += kPartBlock)
@@ -503,6 +508,8 @@ int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
   }
 
   s->L.form = s->form;
+  s->L.round_phantoms = s->form == MPC_SPLIT32 ? 1 : 0;
+  s->L.wcells = (uint32_t)wcb;
   s->L.walls = (p[0].flags & MPC_WALLS_Z) ? 1 : 0;
   s->L.mbs = (p[0].flags & MPC_MBS) ? 1 : 0;
   s->L.nbox = (uint32_t)nbox;
@@ -623,6 +630,7 @@ int mpc_step_profiled(mpc_sim* s, int64_t nsteps, mpc_kernel_times* acc) {
   }
   for (int64_t k = 0; k < nsteps; ++k) {
     HIPCHK(s, launch_scan(s->dev, s->L));
+    HIPCHK(s, launch_phantoms(s->dev, s->L));
     HIPCHK(s, mark());
     HIPCHK(s, launch_scatter(s->dev, s->L));
     HIPCHK(s, mark());

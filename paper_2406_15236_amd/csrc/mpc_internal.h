@@ -42,7 +42,8 @@ struct BoxDev {
   double kT, mass, density, sd;  // sd = sqrt(kT / m)
   double gh[3];        // g * h
   uint32_t grav;
-  uint32_t pad1;
+  uint32_t wcbase;     // walls: first index of this box's cells of the two
+                       // wall-cut layers (2 L0 L1 per box) in a flat index space
 };
 
 struct Tile {          // one collide work item: cells [c0, c0 + nc) of box `box`
@@ -67,6 +68,13 @@ struct Ctrl {          // device-resident step state, read by every kernel
 struct CellDraw {       // random draws of one cell for the current step
   double n[3];         // rotation axis
   double Ek;           // thermostat target energy, 0 = no scaling
+};
+
+struct PhantomSums {   // phantom particles of an occupied wall-cut cell
+  double v[3];         // sum of their velocities
+  double v2;           // sum of |v|^2
+  double n;            // their number
+  double pad;
 };
 
 // State buffers of one form, SoA.  F64: a[0..2]=x (double), b[0..2]=v (double);
@@ -97,16 +105,19 @@ struct Dev {           // device pointers carved from the workspace
   PBlock* pblocks;
   double* partials;    // per-block observable partial sums
   CellDraw* draws;     // per-cell draws of the current step (written by the scan)
+  PhantomSums* phs;    // walls only: phantom sums of wall-cut cells (written by the scan)
   uint32_t ntot;       // particles over all boxes (bound of every particle index)
 };
 
 struct Launch {
   int form;
+  int round_phantoms;      // split form: phantom velocities rounded to FP32
   int walls, mbs;          // feature flags (identical for all boxes)
   uint32_t nbox;
   uint64_t ntot, ctot;     // particles, cells over all boxes
   uint32_t ntiles, npblocks, nscan;
   uint32_t collide_grid;
+  uint32_t wcells;         // walls: cells of the wall-cut layers over all boxes
   int xcd_remap;
   hipStream_t stream;
 };
@@ -116,6 +127,7 @@ hipError_t launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s);
 hipError_t launch_key_hist(const Dev& d, const Launch& l);
 hipError_t launch_scan(const Dev& d, const Launch& l);
 hipError_t launch_scatter(const Dev& d, const Launch& l);
+hipError_t launch_phantoms(const Dev& d, const Launch& l);
 hipError_t launch_collide(const Dev& d, const Launch& l);
 hipError_t launch_advance(const Dev& d, const Launch& l);
 hipError_t launch_set_ctrl(const Dev& d, const Launch& l, uint64_t step, uint32_t cur,

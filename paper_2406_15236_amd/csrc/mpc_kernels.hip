@@ -834,6 +834,59 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(Dev d, uint32_t nblk, ui
 // Scatter: slot of each particle inside its cell segment (order inside a
 // segment is arbitrary here and made canonical in collide).
 // ---------------------------------------------------------------------------
+// Phantom particles of the occupied cells of the two wall-cut layers of every
+// box (one thread per cell of those layers): count, velocity sum and squared-
+// speed sum (velocities N(0, kT/m) per component; rounded to FP32 for the
+// split form), read by the collide's cell sums.
+__global__ __launch_bounds__(kThreads) void k_phantom_sums(Dev d, uint32_t nbox, uint32_t wcells,
+                                                           int round32) {
+  const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= wcells) return;
+  uint32_t lo = 0, hi = nbox;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (d.boxes[mid].wcbase <= i) {
+      lo = mid;
+    } else {
+      hi = mid;
+    }
+  }
+  BoxRef B = as_const(d.boxes)[lo];
+  const uint64_t t = as_const(d.ctrl)->step;
+  double sh[3];
+  shift_of(B, t, sh);
+  const uint32_t plane = (uint32_t)B.L[0] * (uint32_t)B.L[1];
+  const uint32_t li = i - B.wcbase;
+  const uint32_t top = li / plane;
+  const int H = B.L[2];
+  // key layer (c_z + 1) of the cut cells: c_z in {0, H} for s_z >= 0, {-1, H-1} else
+  const int czk = sh[2] >= 0.0 ? (top ? H + 1 : 1) : (top ? H : 0);
+  const uint32_t lkey = (uint32_t)czk * plane + (li - top * plane);
+  const uint32_t c = B.cbase + lkey;
+  if (d.offset[c + 1] == d.offset[c]) return;  // not occupied: no collision
+  const double fw = wall_fraction(sh[2], czk - 1, H);
+  if (!(fw > 0.0)) return;
+  const int nph = phantom_count(B, t, lkey, fw);
+  PhantomSums ps;
+  ps.v[0] = ps.v[1] = ps.v[2] = 0.0;
+  ps.v2 = 0.0;
+  PhantomCache pc;
+  pc.j = 0xffffffffu;
+#pragma unroll 1
+  for (int q = 0; q < nph; ++q) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double vp = B.sd * phantom_normal(B, t, lkey, 3 * q + k, pc);
+      if (round32) vp = (double)(float)vp;
+      ps.v[k] = ps.v[k] + vp;
+      ps.v2 = ps.v2 + vp * vp;
+    }
+  }
+  ps.n = (double)nph;
+  ps.pad = 0.0;
+  d.phs[c] = ps;
+}
+
 __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t* __restrict__ key,
                                                       const uint16_t* __restrict__ rank,
                                                       const uint32_t* __restrict__ offset,
@@ -921,10 +974,12 @@ __device__ __forceinline__ void rotation_matrix(BoxRef B, const double (&n)[3], 
   R[8] = kappa * (ca + omc * n[2] * n[2]);
 }
 
-// Sums and random draws of one cell, one thread per cell.  Velocities of the
-// cell's fluid particles are sv[k][b..e) in canonical order.
+// Sums of one cell, one thread per cell.  Velocities of the cell's fluid
+// particles are sv[k][b..e) in canonical order; a wall-cut cell adds its
+// phantoms' sums (ph, drawn by the scan).
 template <int F, bool W, bool M>
-__device__ void cell_work(BoxRef B, uint64_t t, uint32_t lkey, double sz, const CellDraw& cd,
+__device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd,
+                          const PhantomSums* __restrict__ ph,
                           const typename Form<F>::Vs* __restrict__ sv0,
                           const typename Form<F>::Vs* __restrict__ sv1,
                           const typename Form<F>::Vs* __restrict__ sv2, uint32_t b, uint32_t e,
@@ -937,13 +992,19 @@ __device__ void cell_work(BoxRef B, uint64_t t, uint32_t lkey, double sz, const 
 #pragma unroll
   for (int k = 0; k < 9; ++k) out.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
   if (nf == 0) return;
-  int nph = 0;
+  uint32_t nph = 0;
+  double pv[3] = {0.0, 0.0, 0.0}, pv2 = 0.0;
   if (W) {
     const int cz = (int)(lkey / (uint32_t)(B.L[0] * B.L[1])) - 1;
-    const double fw = wall_fraction(sz, cz, B.L[2]);
-    if (fw > 0.0) nph = phantom_count(B, t, lkey, fw);
+    if (wall_fraction(sz, cz, B.L[2]) > 0.0) {
+      nph = (uint32_t)ph->n;
+      pv[0] = ph->v[0];
+      pv[1] = ph->v[1];
+      pv[2] = ph->v[2];
+      pv2 = ph->v2;
+    }
   }
-  const uint32_t ntot = nf + (uint32_t)nph;
+  const uint32_t ntot = nf + nph;
   const double m = B.mass;
   double V[3];
   if constexpr (F == kFormSplit) {
@@ -966,13 +1027,8 @@ __device__ void cell_work(BoxRef B, uint64_t t, uint32_t lkey, double sz, const 
       add(2, mf * sv2[q]);
     }
     if (W && nph) {
-      PhantomCache pc;
-      pc.j = 0xffffffffu;
-#pragma unroll 1
-      for (int q = 0; q < nph; ++q)
-#pragma unroll 1
-        for (int k = 0; k < 3; ++k)
-          add(k, mf * (float)(B.sd * phantom_normal(B, t, lkey, 3 * q + k, pc)));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) add(k, (float)(m * pv[k]));
     }
     const float Mf = (float)ntot * mf;
 #pragma unroll
@@ -986,13 +1042,8 @@ __device__ void cell_work(BoxRef B, uint64_t t, uint32_t lkey, double sz, const 
       P[2] = P[2] + m * (double)sv2[q];
     }
     if (W && nph) {
-      PhantomCache pc;
-      pc.j = 0xffffffffu;
-#pragma unroll 1
-      for (int q = 0; q < nph; ++q)
-#pragma unroll 1
-        for (int k = 0; k < 3; ++k)
-          P[k] = P[k] + m * (B.sd * phantom_normal(B, t, lkey, 3 * q + k, pc));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) P[k] = P[k] + m * pv[k];
     }
     const double Mtot = (double)ntot * m;
     V[0] = P[0] / Mtot;
@@ -1015,19 +1066,10 @@ __device__ void cell_work(BoxRef B, uint64_t t, uint32_t lkey, double sz, const 
       K = K + m * (dx * dx + dy * dy + dz * dz);
     }
     if (W && nph) {
-      PhantomCache pc;
-      pc.j = 0xffffffffu;
-#pragma unroll 1
-      for (int q = 0; q < nph; ++q) {
-        double d2[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          double vp = B.sd * phantom_normal(B, t, lkey, 3 * q + k, pc);
-          if constexpr (F == kFormSplit) vp = (double)(float)vp;
-          d2[k] = vp - V[k];
-        }
-        K = K + m * (d2[0] * d2[0] + d2[1] * d2[1] + d2[2] * d2[2]);
-      }
+      // sum over phantoms of m |v - V|^2 from their velocity sums
+      const double vV = pv[0] * V[0] + pv[1] * V[1] + pv[2] * V[2];
+      const double VV = V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
+      K = K + m * (pv2 - 2.0 * vV + (double)nph * VV);
     }
     if (K > 0.0) kappa = sqrt((2.0 * cd.Ek) / K);
   }
@@ -1299,8 +1341,8 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
           cd.n[0] = cd.n[1] = cd.n[2] = 0.0;
           cd.Ek = 0.0;
         }
-        cell_work<F, W, M>(B, t, lkey0 + c, s_sh[2], cd, s_v[0], s_v[1], s_v[2], b, e,
-                           s_cell[c - cs]);
+        cell_work<F, W, M>(B, lkey0 + c, s_sh[2], cd, W ? d.phs + T.c0 + c : nullptr, s_v[0],
+                           s_v[1], s_v[2], b, e, s_cell[c - cs]);
       }
       wave_sync();
 
@@ -1736,6 +1778,13 @@ hipError_t launch_scan(const Dev& d, const Launch& l) {
     case 2: hipLaunchKernelGGL((k_scan_down<true, false>), g, b, 0, l.stream, d, nb, nx, ct); break;
     default: hipLaunchKernelGGL((k_scan_down<true, true>), g, b, 0, l.stream, d, nb, nx, ct); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_phantoms(const Dev& d, const Launch& l) {
+  if (!l.walls || l.wcells == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_phantom_sums, dim3((l.wcells + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     l.stream, d, l.nbox, l.wcells, l.round_phantoms);
   return hipGetLastError();
 }
 
