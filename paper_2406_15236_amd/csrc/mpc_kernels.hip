@@ -974,27 +974,28 @@ __device__ __forceinline__ void rotation_matrix(BoxRef B, const double (&n)[3], 
   R[8] = kappa * (ca + omc * n[2] * n[2]);
 }
 
-// Sums of one cell, one thread per cell.  Velocities of the cell's fluid
-// particles are sv[k][b..e) in canonical order; a wall-cut cell adds its
-// phantoms' sums (ph, drawn by the scan).
+// Sums of one cell by a pair of lanes (lane bit 0 = half): each lane sums
+// half of the cell's fluid particles, sv[k][b..e) in canonical order (first
+// half, then second), and the pair combines the halves in that order, so both
+// lanes hold identical totals.  A wall-cut cell adds its phantoms' sums (ph,
+// drawn by k_phantom_sums).  Every lane of the wavefront calls this (the pair
+// exchanges values); only the first lane of a valid pair writes `out`.
+__device__ __forceinline__ double pair_xor(double x) { return __shfl_xor(x, 1, 64); }
+__device__ __forceinline__ float pair_xor(float x) { return __shfl_xor(x, 1, 64); }
+
 template <int F, bool W, bool M>
 __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd,
                           const PhantomSums* __restrict__ ph,
                           const typename Form<F>::Vs* __restrict__ sv0,
                           const typename Form<F>::Vs* __restrict__ sv1,
                           const typename Form<F>::Vs* __restrict__ sv2, uint32_t b, uint32_t e,
-                          CellLds& out) {
-  const uint32_t nf = e - b;
-  // cells that do not collide keep v exactly: V = 0, R = I in the update
-  out.active = 0u;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) out.V[k] = 0.0;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) out.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
-  if (nf == 0) return;
+                          uint32_t half, bool valid, CellLds* out) {
+  const uint32_t nf = valid ? e - b : 0u;
+  const uint32_t mid = b + (nf + 1) / 2;
+  const uint32_t qb = half ? mid : b, qe = valid ? (half ? e : mid) : b;
   uint32_t nph = 0;
   double pv[3] = {0.0, 0.0, 0.0}, pv2 = 0.0;
-  if (W) {
+  if (W && valid && nf > 0) {
     const int cz = (int)(lkey / (uint32_t)(B.L[0] * B.L[1])) - 1;
     if (wall_fraction(sz, cz, B.L[2]) > 0.0) {
       nph = (uint32_t)ph->n;
@@ -1021,59 +1022,89 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
       s[k] = tt;
     };
 #pragma unroll 4
-    for (uint32_t q = b; q < e; ++q) {
+    for (uint32_t q = qb; q < qe; ++q) {
       add(0, mf * sv0[q]);
       add(1, mf * sv1[q]);
       add(2, mf * sv2[q]);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float os = pair_xor(s[k]), oc = pair_xor(c[k]);
+      // first half's (s, c), then the second half's s added, then its c
+      const float s0 = half ? os : s[k], c0 = half ? oc : c[k];
+      const float s1 = half ? s[k] : os, c1 = half ? c[k] : oc;
+      s[k] = s0;
+      c[k] = c0;
+      add(k, s1);
+      c[k] += c1;
     }
     if (W && nph) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) add(k, (float)(m * pv[k]));
     }
-    const float Mf = (float)ntot * mf;
+    const float Mf = (float)(ntot ? ntot : 1u) * mf;
 #pragma unroll
     for (int k = 0; k < 3; ++k) V[k] = (double)((s[k] + c[k]) / Mf);
   } else {
     double P[3] = {0.0, 0.0, 0.0};
 #pragma unroll 4
-    for (uint32_t q = b; q < e; ++q) {
+    for (uint32_t q = qb; q < qe; ++q) {
       P[0] = P[0] + m * (double)sv0[q];
       P[1] = P[1] + m * (double)sv1[q];
       P[2] = P[2] + m * (double)sv2[q];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double o = pair_xor(P[k]);
+      P[k] = half ? o + P[k] : P[k] + o;
     }
     if (W && nph) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) P[k] = P[k] + m * pv[k];
     }
-    const double Mtot = (double)ntot * m;
+    const double Mtot = (double)(ntot ? ntot : 1u) * m;
     V[0] = P[0] / Mtot;
     V[1] = P[1] / Mtot;
     V[2] = P[2] / Mtot;
   }
-  if (ntot < 2) return;
-  out.V[0] = V[0];
-  out.V[1] = V[1];
-  out.V[2] = V[2];
-  out.active = 1u;
-  const double n[3] = {cd.n[0], cd.n[1], cd.n[2]};
   double kappa = 1.0;
-  if (M && cd.Ek > 0.0) {
+  if (M) {
     double K = 0.0;
 #pragma unroll 4
-    for (uint32_t q = b; q < e; ++q) {
+    for (uint32_t q = qb; q < qe; ++q) {
       const double dx = (double)sv0[q] - V[0], dy = (double)sv1[q] - V[1],
                    dz = (double)sv2[q] - V[2];
       K = K + m * (dx * dx + dy * dy + dz * dz);
     }
+    const double oK = pair_xor(K);
+    K = half ? oK + K : K + oK;
     if (W && nph) {
       // sum over phantoms of m |v - V|^2 from their velocity sums
       const double vV = pv[0] * V[0] + pv[1] * V[1] + pv[2] * V[2];
       const double VV = V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
       K = K + m * (pv2 - 2.0 * vV + (double)nph * VV);
     }
-    if (K > 0.0) kappa = sqrt((2.0 * cd.Ek) / K);
+    if (cd.Ek > 0.0 && K > 0.0) kappa = sqrt((2.0 * cd.Ek) / K);
   }
-  rotation_matrix(B, n, kappa, out.R);
+  if (!valid || half) return;
+  // cells that do not collide keep v exactly: V = 0, R = I in the update
+  if (nf == 0 || ntot < 2) {
+    out->active = 0u;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out->V[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) out->R[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    return;
+  }
+  out->V[0] = V[0];
+  out->V[1] = V[1];
+  out->V[2] = V[2];
+  out->active = 1u;
+  const double n[3] = {cd.n[0], cd.n[1], cd.n[2]};
+  double R[9];
+  rotation_matrix(B, n, kappa, R);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) out->R[k] = R[k];
 }
 
 // The collide workgroup is a single wavefront.  LDS instructions of one wave
@@ -1107,6 +1138,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   constexpr int NT = kCollideThreads;
   constexpr int NS = kTileCap / kCollideThreads;
   static_assert(kTileMaxCells < NT, "one lane per cell offset (nc + 1) of a tile");
+  static_assert(2 * kTileMaxCells <= NT, "two lanes per cell in the cell sums");
   static_assert(NT == 64, "the workgroup is one wavefront (see wave_sync)");
   __shared__ uint32_t s_off[kTileMaxCells + 1];
   __shared__ uint32_t s_idx[kTileCap];   // perm entries, segment order as scattered
@@ -1328,21 +1360,27 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
       }
       wave_sync();
 
-      // Phase C: one lane per cell (the first pass uses the prefetched draws)
-      if (cs + lane < ce) {
-        const uint32_t c = cs + lane;
-        const uint32_t b = s_off[c] - base, e = s_off[c + 1] - base;
+      // Phase C: two lanes per cell (lanes 2j and 2j + 1 for cell cs + j); the
+      // first pass uses the prefetched draws, which lane j holds
+      {
+        const uint32_t j = lane >> 1;
+        const uint32_t c = cs + j;
+        const bool valid = c < ce;
+        const uint32_t b = valid ? s_off[c] - base : 0u, e = valid ? s_off[c + 1] - base : 0u;
         CellDraw cd;
-        if (use_pf) {
-          cd = draw_cur;
-        } else if (e > b) {
-          cd = d.draws[T.c0 + c];
-        } else {
-          cd.n[0] = cd.n[1] = cd.n[2] = 0.0;
-          cd.Ek = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) cd.n[k] = __shfl(draw_cur.n[k], (int)j, 64);
+        cd.Ek = __shfl(draw_cur.Ek, (int)j, 64);
+        if (!use_pf) {
+          if (valid && e > b) {
+            cd = d.draws[T.c0 + c];
+          } else {
+            cd.n[0] = cd.n[1] = cd.n[2] = 0.0;
+            cd.Ek = 0.0;
+          }
         }
-        cell_work<F, W, M>(B, lkey0 + c, s_sh[2], cd, W ? d.phs + T.c0 + c : nullptr, s_v[0],
-                           s_v[1], s_v[2], b, e, s_cell[c - cs]);
+        cell_work<F, W, M>(B, lkey0 + c, s_sh[2], cd, W ? d.phs + T.c0 + (valid ? c : 0u) : nullptr,
+                           s_v[0], s_v[1], s_v[2], b, e, lane & 1u, valid, &s_cell[j]);
       }
       wave_sync();
 
