@@ -17,6 +17,10 @@
  *     particles filling wall-cut cells) and constant gravity (Boundary
  *     conditions, External fields)
  *   - particles periodically reordered by cell (Sec. III.B.3, reordering).
+ *     Here the device keeps the particles in cell order every step; the
+ *     reorder interval R decides when the order seen through mpc_get_state
+ *     is renumbered to (cell, index) order: after every step t with
+ *     (t + 1) mod R = 0 (R = 0: never).
  * The arguments follow the paper's statement of the method: box in cells,
  * cell size a, mean density <N_c>, time step h, rotation angle alpha, k_B T,
  * mass m, and a main random seed (Sec. III.D.4, "passed as a parameter").
@@ -82,8 +86,8 @@ typedef struct {
   int32_t  L[3];          /* box in cells; with MPC_WALLS_Z, L[2] = H                     */
   int32_t  form;          /* mpc_form (same for all boxes)                                 */
   uint32_t flags;         /* MPC_MBS | MPC_WALLS_Z (same for all boxes)                    */
-  int32_t  reorder_every; /* R: store particles in cell order after every R-th step;
-                             0 = never (same for all boxes)                               */
+  int32_t  reorder_every; /* R: renumber particles in (cell, index) order after every
+                             R-th step; 0 = never (same for all boxes)                    */
   double   a;             /* cell size, > 0                                                */
   double   density;       /* <N_c>: N = llround(density * L0 * L1 * L2), > 0              */
   double   dt;            /* MPC time step h, > 0                                          */
@@ -105,7 +109,11 @@ typedef struct {
 } mpc_obs;
 
 /* Per-kernel device time accumulated by mpc_step_profiled (milliseconds,
- * from HIP events recorded on the handle's stream around each launch). */
+ * from HIP events recorded on the handle's stream around each launch):
+ * scan = prefix sum of the cell counts, per-cell random draws and (walls)
+ * phantom sums; scatter = the sort permutation; collide = the collision,
+ * the next step's streaming and binning and the state write; prologue = the
+ * binning of a state set from outside; other = the step-counter advance. */
 typedef struct {
   double scan_ms, scatter_ms, collide_ms, prologue_ms, other_ms;
   uint64_t scan_launches, scatter_launches, collide_launches, prologue_launches;
@@ -170,10 +178,9 @@ int mpc_get_state(mpc_sim* s, int32_t box, double* x, double* v, int64_t n);
 
 /* Binning of the last completed step of one box (synchronises):
  *   offset[ncell+1]: exclusive prefix of particles per cell;
- *   perm[n]: storage index (in the order before that step) of the j-th
- *            particle in (cell key, storage index) order;
- *   key[n]:  cell key of each particle, indexed by the storage order before
- *            that step.
+ *   perm[n]: index (in the particle order of mpc_get_state before that step)
+ *            of the j-th particle in (cell key, index) order;
+ *   key[n]:  cell key of each particle, indexed by that same order.
  * Keys are x-fastest: ((c_z' * L1) + c_y) * L0 + c_x with c_z' = c_z (periodic)
  * or c_z + 1 (walls).  Any pointer may be NULL.  MPC_EINVAL if no step has
  * run since the state was set. */

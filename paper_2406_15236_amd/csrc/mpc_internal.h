@@ -95,7 +95,7 @@ struct Dev {           // device pointers carved from the workspace
   StatePtrs S[2];
   uint32_t* key;       // cell key per particle (storage order)
   uint16_t* rank;      // rank of the particle among those counted for its key
-  uint32_t* perm;      // sorted slot -> storage index
+  uint32_t* perm;      // position in (cell, any order) -> stored slot
   uint32_t* hist;      // particles per cell of the next step; zeroed by the scan
   uint32_t* offset;    // exclusive prefix, ncell + 1
   uint32_t* scan_blk;  // per scan-block totals

@@ -583,23 +583,6 @@ __global__ void k_advance(Ctrl* c) {
 }
 
 // hist[c] += 1 for every active lane, one atomic per distinct key in the
-// wavefront (issued by the lowest lane carrying that key).
-__device__ __forceinline__ void wave_hist_add(uint32_t* hist, uint32_t c, bool active) {
-  const uint32_t lane = threadIdx.x & 63;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint64_t pending = __ballot(active);
-  uint64_t mine = 0;
-  while (pending) {
-    const int lead = __ffsll((unsigned long long)pending) - 1;
-    const uint32_t lc = (uint32_t)__builtin_amdgcn_readlane((int)c, lead);
-    const uint64_t same = __ballot(active && c == lc) & pending;
-    if (active && c == lc) mine = same;
-    pending &= ~same;
-  }
-  if (active && (mine & lt_mask) == 0ull) atomicAdd(&hist[c], (uint32_t)__popcll(mine));
-}
-
-// hist[c] += 1 for every active lane, one atomic per distinct key in the
 // wavefront; returns the lane's rank among all particles counted for c (the
 // old count of its run's leader plus its place in the run).
 __device__ __forceinline__ uint32_t wave_hist_rank(uint32_t* hist, uint32_t c, bool active) {
@@ -1159,8 +1142,9 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   const uint64_t t = as_const(d.ctrl)->step;
   const uint32_t cur = as_const(d.ctrl)->cur;
   const int32_t R = as_const(d.ctrl)->reorder;
-  // the state is always written in cell order into the other buffer; logical
-  // indices are renumbered to that order on reorder steps
+  // the state is always written into the other buffer (cell by cell, each
+  // tile pass grouped by next-step cell); logical indices are renumbered to
+  // the canonical (cell, index) order on reorder steps
   const bool renumber = R > 0 && (t + 1) % (uint64_t)R == 0;
   const StatePtrs in = d.S[cur];
   const StatePtrs out = d.S[cur ^ 1u];
@@ -1310,7 +1294,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
       }
       wave_sync();
 
-      // Phase B: gather, canonical position (rank by storage index inside
+      // Phase B: gather, canonical position (rank by logical index inside
       // the cell), stream of step t, park in LDS.
       {
         typename Fm::P p[NS];
