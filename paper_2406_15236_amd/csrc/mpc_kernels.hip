@@ -1276,16 +1276,12 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
         continue;
       }
 
-      // Phase A: segment entries (prefetched for the first pass), their
-      // logical indices and their cell
+      // Phase A: segment entries (prefetched for the first pass) and their
+      // cell
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
         const uint32_t q = lane + k * NT;
-        if (q < np) {
-          const uint32_t pe = use_pf ? perm_cur[k] : d.perm[base + q];
-          s_idx[q] = pe;
-          if (track) s_rk[q] = pe < d.ntot ? in.id[pe] : 0u;
-        }
+        if (q < np) s_idx[q] = use_pf ? perm_cur[k] : d.perm[base + q];
       }
       if (cs + lane < ce) {
         const uint32_t c = cs + lane;
@@ -1297,16 +1293,20 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
       // Phase B: gather, canonical position (rank by logical index inside
       // the cell), stream of step t, park in LDS.
       {
+        // the logical indices are gathered with the state (one memory round
+        // trip per pass), then put in LDS for the in-cell ranking
         typename Fm::P p[NS];
         typename Fm::Vv v[NS];
-        uint32_t ii[NS];
+        uint32_t ii[NS], idk[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
           const uint32_t q = lane + k * NT;
           ii[k] = 0;
+          idk[k] = 0;
           if (q < np) {
             ii[k] = s_idx[q] < d.ntot ? s_idx[q] : 0u;
             Fm::load(in, ii[k], p[k], v[k]);
+            if (track) idk[k] = in.id[ii[k]];
           }
         }
         // prefetch the next tile's first-pass perm entries and cell draws
@@ -1322,6 +1322,14 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             perm_next[k] = (q < nn && nb + q < d.ntot) ? d.perm[nb + q] : 0u;
           }
           if (lane < Tn.nc) draw_next = d.draws[Tn.c0 + lane];
+        }
+        if (track) {
+#pragma unroll
+          for (int k = 0; k < NS; ++k) {
+            const uint32_t q = lane + k * NT;
+            if (q < np) s_rk[q] = idk[k];
+          }
+          wave_sync();
         }
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
