@@ -936,25 +936,20 @@ __device__ __forceinline__ uint32_t rank_in_segment(const uint32_t* seg, uint32_
 
 struct CellLds {
   double V[3];   // centre-of-mass velocity
-  double R[9];   // kappa * rotation matrix, row major
-  uint32_t active;
-  uint32_t pad;
+  double n[3];   // rotation axis
+  double kappa;  // thermostat scale; 0 = the cell does not collide
 };
 
-// kappa * R(alpha, n): R = cos(a) I + sin(a) [n]x + (1 - cos(a)) n n^T, so that
-// R u = cos(a) u + sin(a) n x u + (1 - cos(a)) (n . u) n  (Eq. 2).
-__device__ __forceinline__ void rotation_matrix(BoxRef B, const double (&n)[3], double kappa,
-                                                double (&R)[9]) {
-  const double ca = B.ca, sa = B.sa, omc = B.omc;
-  R[0] = kappa * (ca + omc * n[0] * n[0]);
-  R[1] = kappa * (omc * n[0] * n[1] - sa * n[2]);
-  R[2] = kappa * (omc * n[0] * n[2] + sa * n[1]);
-  R[3] = kappa * (omc * n[1] * n[0] + sa * n[2]);
-  R[4] = kappa * (ca + omc * n[1] * n[1]);
-  R[5] = kappa * (omc * n[1] * n[2] - sa * n[0]);
-  R[6] = kappa * (omc * n[2] * n[0] - sa * n[1]);
-  R[7] = kappa * (omc * n[2] * n[1] + sa * n[0]);
-  R[8] = kappa * (ca + omc * n[2] * n[2]);
+// Rotation by alpha about n (Eq. 2): R u = cos(a) u + sin(a) n x u +
+// (1 - cos(a)) (n . u) n.
+template <typename T>
+__device__ __forceinline__ void rotate(T ca, T sa, T omc, const T (&n)[3], const T (&u)[3],
+                                       T (&r)[3]) {
+  const T nu = n[0] * u[0] + n[1] * u[1] + n[2] * u[2];
+  const T cx[3] = {n[1] * u[2] - n[2] * u[1], n[2] * u[0] - n[0] * u[2],
+                   n[0] * u[1] - n[1] * u[0]};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) r[a] = ca * u[a] + sa * cx[a] + omc * nu * n[a];
 }
 
 // Sums of one cell by a pair of lanes (lane bit 0 = half): each lane sums
@@ -1070,24 +1065,14 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
     if (cd.Ek > 0.0 && K > 0.0) kappa = sqrt((2.0 * cd.Ek) / K);
   }
   if (!valid || half) return;
-  // cells that do not collide keep v exactly: V = 0, R = I in the update
-  if (nf == 0 || ntot < 2) {
-    out->active = 0u;
+  // cells that do not collide keep v exactly (kappa = 0 marks them)
+  const bool coll = nf > 0 && ntot >= 2;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) out->V[k] = 0.0;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) out->R[k] = (k % 4 == 0) ? 1.0 : 0.0;
-    return;
+  for (int k = 0; k < 3; ++k) {
+    out->V[k] = coll ? V[k] : 0.0;
+    out->n[k] = coll ? cd.n[k] : 0.0;
   }
-  out->V[0] = V[0];
-  out->V[1] = V[1];
-  out->V[2] = V[2];
-  out->active = 1u;
-  const double n[3] = {cd.n[0], cd.n[1], cd.n[2]};
-  double R[9];
-  rotation_matrix(B, n, kappa, R);
-#pragma unroll
-  for (int k = 0; k < 9; ++k) out->R[k] = R[k];
+  out->kappa = coll ? kappa : 0.0;
 }
 
 // The collide workgroup is a single wavefront.  LDS instructions of one wave
@@ -1394,15 +1379,15 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
           v.v[2] = s_v[2][q];
           const CellLds& C = s_cell[s_lc[q]];
           if constexpr (F == kFormSplit) {
-            {
+            if (C.kappa != 0.0) {
               const float V[3] = {(float)C.V[0], (float)C.V[1], (float)C.V[2]};
+              const float nf3[3] = {(float)C.n[0], (float)C.n[1], (float)C.n[2]};
+              const float kf = (float)C.kappa;
               const float u[3] = {v.v[0] - V[0], v.v[1] - V[1], v.v[2] - V[2]};
+              float r[3];
+              rotate<float>((float)B.ca, (float)B.sa, (float)B.omc, nf3, u, r);
 #pragma unroll
-              for (int a = 0; a < 3; ++a) {
-                const float r0 = (float)C.R[3 * a], r1 = (float)C.R[3 * a + 1],
-                            r2 = (float)C.R[3 * a + 2];
-                v.v[a] = V[a] + fmaf(r0, u[0], fmaf(r1, u[1], r2 * u[2]));
-              }
+              for (int a = 0; a < 3; ++a) v.v[a] = V[a] + kf * r[a];
             }
             if (B.grav) {
 #pragma unroll
@@ -1410,12 +1395,13 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             }
           } else {
             double w[3] = {(double)v.v[0], (double)v.v[1], (double)v.v[2]};
-            {
+            if (C.kappa != 0.0) {
               const double u[3] = {w[0] - C.V[0], w[1] - C.V[1], w[2] - C.V[2]};
+              const double nd[3] = {C.n[0], C.n[1], C.n[2]};
+              double r[3];
+              rotate<double>(B.ca, B.sa, B.omc, nd, u, r);
 #pragma unroll
-              for (int a = 0; a < 3; ++a)
-                w[a] = C.V[a] +
-                       fma(C.R[3 * a], u[0], fma(C.R[3 * a + 1], u[1], C.R[3 * a + 2] * u[2]));
+              for (int a = 0; a < 3; ++a) w[a] = C.V[a] + C.kappa * r[a];
             }
             if (B.grav) {
 #pragma unroll
