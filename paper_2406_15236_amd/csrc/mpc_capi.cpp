@@ -256,8 +256,11 @@ void build_tiles(mpc_sim* s) {
                    [](const Keyed& a, const Keyed& b) { return a.k < b.k; });
   for (const Keyed& kt : keyed) s->tiles.push_back(kt.t);
   s->L.ntiles = (uint32_t)s->tiles.size();
+  // default persistent grid: at most 8 one-wave workgroups per CU in flight
+  // (more waves per XCD evict the gathered rows from L2), oversubscribed 2x
+  // so that freed slots take the remaining workgroups (tail balance)
   uint32_t g = s->grid_override ? (uint32_t)s->grid_override
-                                : (uint32_t)(s->num_cu * std::max(1, s->occupancy));
+                                : (uint32_t)(2 * s->num_cu * std::min(8, std::max(1, s->occupancy)));
   g = std::max<uint32_t>(1, std::min<uint32_t>(g, s->L.ntiles));
   s->L.collide_grid = g;
 }

@@ -934,10 +934,28 @@ __device__ __forceinline__ uint32_t rank_in_segment(const uint32_t* seg, uint32_
   return r;
 }
 
+// Per-cell record of the collision, FP64 forms: the update rotates with the
+// vector formula in FP64.
 struct CellLds {
   double V[3];   // centre-of-mass velocity
   double n[3];   // rotation axis
   double kappa;  // thermostat scale; 0 = the cell does not collide
+};
+// Split form: kappa R(alpha, n) built in FP64 and rounded to FP32, so the
+// FP32 rotation's rounding differs from cell to cell (FP32 cos and sin of the
+// one angle would bias every collision's energy the same way).
+struct CellLdsSplit {
+  float V[3];
+  float R[9];    // kappa * rotation matrix, row major
+  float coll;    // 0 = the cell does not collide
+};
+template <int F>
+struct CellRec {
+  using T = CellLds;
+};
+template <>
+struct CellRec<kFormSplit> {
+  using T = CellLdsSplit;
 };
 
 // Rotation by alpha about n (Eq. 2): R u = cos(a) u + sin(a) n x u +
@@ -967,7 +985,7 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
                           const typename Form<F>::Vs* __restrict__ sv0,
                           const typename Form<F>::Vs* __restrict__ sv1,
                           const typename Form<F>::Vs* __restrict__ sv2, uint32_t b, uint32_t e,
-                          uint32_t half, bool valid, CellLds* out) {
+                          uint32_t half, bool valid, typename CellRec<F>::T* out) {
   const uint32_t nf = valid ? e - b : 0u;
   const uint32_t mid = b + (nf + 1) / 2;
   const uint32_t qb = half ? mid : b, qe = valid ? (half ? e : mid) : b;
@@ -1065,14 +1083,29 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
     if (cd.Ek > 0.0 && K > 0.0) kappa = sqrt((2.0 * cd.Ek) / K);
   }
   if (!valid || half) return;
-  // cells that do not collide keep v exactly (kappa = 0 marks them)
+  // cells that do not collide keep v exactly (kappa = 0 / coll = 0 marks them)
   const bool coll = nf > 0 && ntot >= 2;
+  if constexpr (F == kFormSplit) {
+    const double n[3] = {cd.n[0], cd.n[1], cd.n[2]};
+    const double ca = B.ca, sa = B.sa, omc = B.omc;
+    const double R[9] = {ca + omc * n[0] * n[0],        omc * n[0] * n[1] - sa * n[2],
+                         omc * n[0] * n[2] + sa * n[1], omc * n[1] * n[0] + sa * n[2],
+                         ca + omc * n[1] * n[1],        omc * n[1] * n[2] - sa * n[0],
+                         omc * n[2] * n[0] - sa * n[1], omc * n[2] * n[1] + sa * n[0],
+                         ca + omc * n[2] * n[2]};
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    out->V[k] = coll ? V[k] : 0.0;
-    out->n[k] = coll ? cd.n[k] : 0.0;
+    for (int k = 0; k < 3; ++k) out->V[k] = coll ? (float)V[k] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) out->R[k] = coll ? (float)(kappa * R[k]) : 0.0f;
+    out->coll = coll ? 1.0f : 0.0f;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      out->V[k] = coll ? V[k] : 0.0;
+      out->n[k] = coll ? cd.n[k] : 0.0;
+    }
+    out->kappa = coll ? kappa : 0.0;
   }
-  out->kappa = coll ? kappa : 0.0;
 }
 
 // The collide workgroup is a single wavefront.  LDS instructions of one wave
@@ -1116,7 +1149,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   __shared__ Vs s_v[3][kTileCap];        // streamed velocities, canonical order
   __shared__ Xs s_x[3][kTileCap];        // streamed positions (offsets), canonical order
   __shared__ uint32_t s_c[Fm::kHasCell ? kTileCap : 1];
-  __shared__ CellLds s_cell[kTileMaxCells];
+  __shared__ typename CellRec<F>::T s_cell[kTileMaxCells];
   __shared__ double s_sh[6];
   // next-step window of the tile: cells x0-1 .. x0+nc of the rows (y0 +- 1,
   // z0 +- 1), plus one entry for particles that leave it; per pass: counts,
@@ -1377,17 +1410,13 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
           v.v[0] = s_v[0][q];
           v.v[1] = s_v[1][q];
           v.v[2] = s_v[2][q];
-          const CellLds& C = s_cell[s_lc[q]];
+          const auto& C = s_cell[s_lc[q]];
           if constexpr (F == kFormSplit) {
-            if (C.kappa != 0.0) {
-              const float V[3] = {(float)C.V[0], (float)C.V[1], (float)C.V[2]};
-              const float nf3[3] = {(float)C.n[0], (float)C.n[1], (float)C.n[2]};
-              const float kf = (float)C.kappa;
-              const float u[3] = {v.v[0] - V[0], v.v[1] - V[1], v.v[2] - V[2]};
-              float r[3];
-              rotate<float>((float)B.ca, (float)B.sa, (float)B.omc, nf3, u, r);
+            if (C.coll != 0.0f) {
+              const float u[3] = {v.v[0] - C.V[0], v.v[1] - C.V[1], v.v[2] - C.V[2]};
 #pragma unroll
-              for (int a = 0; a < 3; ++a) v.v[a] = V[a] + kf * r[a];
+              for (int a = 0; a < 3; ++a)
+                v.v[a] = C.V[a] + fmaf(C.R[3 * a], u[0], fmaf(C.R[3 * a + 1], u[1], C.R[3 * a + 2] * u[2]));
             }
             if (B.grav) {
 #pragma unroll

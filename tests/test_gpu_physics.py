@@ -97,4 +97,6 @@ def test_precision_form_drift(mpc):
         print(f"{form}: 100 steps |dE|/E = {dE:.3e}, max |dP| / sqrt(N) = {dP:.3e}")
         res[form] += (dE, dP)
     assert res["fp64"][2] < 1e-12 and res["fp64"][3] < 1e-12
-    assert res["split"][2] < 1e-5 and res["split"][3] < 1e-5
+    # energy: FP32 rounding of the per-cell rotations must not bias the
+    # energy (a fixed FP32 cos/sin of the angle gives ~1e-6 in 100 steps)
+    assert res["split"][2] < 1e-8 and res["split"][3] < 1e-5
