@@ -113,6 +113,8 @@ def run_c3(mpc, torch, synth, steps: int):
         o0 = sim.observables()
         n = o0["N"]
         sim.step(2)
+        sim.autotune(2)  # state and step restored by the tuner
+        out.setdefault("tiling", {})[form] = sim.get_tiling()
         sim.sync()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -148,6 +150,8 @@ def run_c5(mpc, torch, synth, steps: int):
     nsnap, gap = 10, 200
     run = steps - nsnap * gap
     sim.step(2)
+    sim.autotune(3)  # state and step restored by the tuner
+    tiling = sim.get_tiling()
     sim.sync()
     t0 = time.perf_counter()
     done = 0
@@ -185,7 +189,7 @@ def run_c5(mpc, torch, synth, steps: int):
             "ms_per_step": wall * 1e3 / (run - 2),
             "profile_curvature_vs_theory": A / A_th, "slip_over_vmax": B / (A * H * H / 4),
             "profile_r2": r2, "v_max": A * H * H / 4 + B, "T_end": o["T"],
-            "eta_theory": eta, "profile": [round(float(q), 5) for q in prof]}
+            "eta_theory": eta, "tiling": tiling, "profile": [round(float(q), 5) for q in prof]}
 
 
 def cpu_baseline(seconds_hint: float = 15.0):
