@@ -243,6 +243,9 @@ void build_tiles(mpc_sim* s) {
           t.c0 = B.cbase + (uint32_t)((cz * L1 + cy) * L0 + cx);
           t.nc = (uint16_t)std::min<uint64_t>(T, L0 - cx);
           t.box = (uint16_t)b;
+          t.x0 = (uint32_t)cx;
+          t.y0 = (uint32_t)cy;
+          t.z0 = (uint32_t)cz;
           const uint64_t slab = cz * 8 / (uint64_t)B.nlz;
           const uint64_t k =
               ((((((uint64_t)b * 8 + slab) << 12 | (cy / yb)) << 11 | cz) << 11 | cy) << 12) |
@@ -1025,7 +1028,7 @@ int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* 
   int bestT = T0, bestG = g0, bestY = y0;
   double best = 1e300;
   // coordinate search: tile size, then the persistent grid, then the row block
-  const int Ts[] = {0, 8, 12, 16, 24, 32};
+  const int Ts[] = {0, 8, 12, 16, 20, 22, 24, 28, 32};
   // grids: the resident maximum (0), fixed workgroups per CU (fewer waves
   // in flight per XCD can keep the gathered rows in L2), and oversubscribed
   // grids (freed slots take the remaining workgroups: better tail balance)

@@ -50,6 +50,7 @@ struct Tile {          // one collide work item: cells [c0, c0 + nc) of box `box
   uint32_t c0;         // first global cell key
   uint16_t nc;
   uint16_t box;
+  uint32_t x0, y0, z0; // coordinates of the first cell in its box (z0: key layer)
 };
 
 struct PBlock {        // one block of a per-particle kernel

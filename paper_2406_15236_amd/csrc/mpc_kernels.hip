@@ -38,6 +38,9 @@ __device__ __forceinline__ Tile load_tile(const Tile* p, uint32_t i) {
   t.c0 = r.c0;
   t.nc = r.nc;
   t.box = r.box;
+  t.x0 = r.x0;
+  t.y0 = r.y0;
+  t.z0 = r.z0;
   return t;
 }
 __device__ __forceinline__ PBlock load_pblock(const PBlock* p, uint32_t i) {
@@ -1222,9 +1225,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
     cached_box = T.box;
     const uint32_t lkey0 = T.c0 - B.cbase;
     // tiles lie inside one row: (x0 .. x0 + nc - 1, y0, z0)
-    const int x0 = (int)(lkey0 % (uint32_t)B.L[0]);
-    const int y0 = (int)((lkey0 / (uint32_t)B.L[0]) % (uint32_t)B.L[1]);
-    const int z0 = (int)(lkey0 / (uint32_t)(B.L[0] * B.L[1]));
+    const int x0 = (int)T.x0, y0 = (int)T.y0, z0 = (int)T.z0;
     const int WX = (int)T.nc + 2;
     const int L0 = B.L[0], L1 = B.L[1], L2 = B.L[2];
     // offsets of the tile after next (two ahead)

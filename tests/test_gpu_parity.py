@@ -243,7 +243,7 @@ def test_autotune_keeps_results(mpc):
         tc, grid = sim.autotune(trial_steps=2)
         print(f"autotune picked tile_cells={tc} grid={grid}: {sim.get_tiling()}")
         assert sim.get_step() == 2
-        assert tc in (0, 8, 12, 16, 24, 32) and grid > 0
+        assert tc in (0, 8, 12, 16, 20, 22, 24, 28, 32) and grid > 0
         sim.step(4)
         xa, va = sim.get_state()
         ka, pa, oa = sim.get_binning()
