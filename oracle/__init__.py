@@ -38,7 +38,7 @@ def build(out: str = LIB_PATH, src: str = _SRC) -> str:
 
 class _Params(C.Structure):
     _fields_ = [("L", C.c_int32 * 3), ("walls", C.c_int32), ("mbs", C.c_int32),
-                ("pad", C.c_int32), ("h", C.c_double), ("alpha", C.c_double),
+                ("amc", C.c_int32), ("h", C.c_double), ("alpha", C.c_double),
                 ("kT", C.c_double), ("mass", C.c_double), ("density", C.c_double),
                 ("g", C.c_double * 3), ("seed", C.c_uint64)]
 
@@ -55,12 +55,13 @@ class Params:
     seed: int = 1
     mbs: bool = False
     walls: bool = False
+    amc: bool = False
     g: tuple = field(default_factory=lambda: (0.0, 0.0, 0.0))
 
     def c(self) -> _Params:
         p = _Params()
         p.L[:] = [int(v) for v in self.L]
-        p.walls, p.mbs, p.pad = int(self.walls), int(self.mbs), 0
+        p.walls, p.mbs, p.amc = int(self.walls), int(self.mbs), int(self.amc)
         p.h, p.alpha, p.kT, p.mass = self.h, self.alpha, self.kT, self.mass
         p.density = self.density
         p.g[:] = [float(v) for v in self.g]
@@ -129,7 +130,7 @@ def load(path: str):
             "orc_phantoms": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.c_double, f64p,
                                          C.c_int32]),
             "orc_rotate": (None, [C.c_double, f64p, f64p, f64p]),
-            "orc_collide": (C.c_int, [P, C.c_uint64, C.c_int64, f64p, u32p, u32p,
+            "orc_collide": (C.c_int, [P, C.c_uint64, C.c_int64, f64p, f64p, u32p, u32p,
                                       C.c_int64, f64p]),
             "orc_reorder": (None, [C.c_int64, f64p, f64p, u32p]),
             "orc_step": (C.c_int, [P, C.c_uint64, C.c_int64, f64p, f64p, C.c_int32,
@@ -238,15 +239,22 @@ def sort(key, ncell: int):
     return perm, offset
 
 
-def collide(p: Params, t: int, v, perm, offset, cells: bool = False):
-    """Eq.(2) + MBS on streamed velocities v (3, n).  Returns v' [, cell table]."""
+def collide(p: Params, t: int, v, perm, offset, cells: bool = False, x=None):
+    """Eq.(2) + MBS (or Eqs. 3-4, SRD+a, which reads the streamed positions x)
+    on streamed velocities v (3, n).  Returns v' [, cell table]."""
     v = np.ascontiguousarray(v, dtype=np.float64).copy()
     perm = np.ascontiguousarray(perm, dtype=np.uint32)
     offset = np.ascontiguousarray(offset, dtype=np.uint32)
     ncell = offset.size - 1
     co = np.zeros(ncell * CELL_STRIDE) if cells else None
-    lib().orc_collide(C.byref(p.c()), t, v.shape[1], _f64(v), _u32(perm), _u32(offset),
-                      ncell, _f64(co) if cells else None)
+    xp = None
+    if x is not None:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        xp = _f64(x)
+    rc = lib().orc_collide(C.byref(p.c()), t, v.shape[1], xp, _f64(v), _u32(perm),
+                           _u32(offset), ncell, _f64(co) if cells else None)
+    if rc != 0:
+        raise ValueError("SRD+a needs positions and is defined without walls and thermostat")
     if cells:
         return v, co.reshape(ncell, CELL_STRIDE)
     return v
@@ -269,6 +277,8 @@ def step(p: Params, t: int, x, v, reorder: bool = False, binning: bool = False):
     offset = np.zeros(p.ncells + 1, dtype=np.uint32)
     rc = lib().orc_step(C.byref(p.c()), t, n, _f64(x), _f64(v), int(bool(reorder)),
                         _u32(key), _u32(perm), _u32(offset))
+    if rc == -2:
+        raise ValueError("SRD+a is defined without walls and thermostat")
     if rc != 0:
         raise ValueError("position outside the box or not finite")
     if binning:

@@ -351,9 +351,97 @@ void orc_rotate(double alpha, const double n[3], const double u[3], double out[3
 /* Cells with fewer than two particles are left unchanged.  Afterwards the    */
 /* gravity kick v <- v + g h is applied to every particle (reading: gravity). */
 /* ------------------------------------------------------------------------ */
-int orc_collide(const orc_params* p, uint64_t t, int64_t n, double* v, const uint32_t* perm,
-                const uint32_t* offset, int64_t ncell, double* cell_out) {
+/* Sec. II Eqs.(3)-(4), SRD+a: after the rotation, each particle also gets
+ * omega x r_ic, with r_ic its position relative to the cell's centre of mass
+ * and omega = m I^-1 sum_i r_ic x (u_i - D u_i) (u_i = v_i - v_cm, D the
+ * rotation, I the cell's inertia tensor about the centre of mass), so that
+ * the cell's angular momentum about its centre of mass is unchanged.
+ * Positions are taken in the cell's frame, (x + s) - floor(x + s), which has
+ * no periodic-image ambiguity.  Readings: a cell of two particles has a
+ * singular I; the change of angular momentum then lies in I's range and the
+ * pseudo-inverse, omega = dL / (m |r_1 - r_2|^2 / 2), is used; three or more
+ * particles use I^-1 (Cramer's rule), and omega = 0 if det I = 0.  Applied for
+ * periodic boxes without the thermostat only. */
+static void amc_cell(const orc_params* p, const double s[3], int64_t n, const double* x,
+                     const double* v0, double* v, const uint32_t* perm, uint32_t b, uint32_t e,
+                     const double V[3], const double ax[3], double ca, double sa, double omc) {
   const double m = p->mass;
+  const int64_t nf = (int64_t)e - (int64_t)b;
+  double rc[3] = {0.0, 0.0, 0.0};
+  for (uint32_t j = b; j < e; ++j) {
+    uint32_t i = perm[j];
+    for (int k = 0; k < 3; ++k) {
+      double y = x[k * n + i] + s[k];
+      rc[k] = rc[k] + (y - floor(y));
+    }
+  }
+  for (int k = 0; k < 3; ++k) rc[k] = rc[k] / (double)nf;
+  double dL[3] = {0.0, 0.0, 0.0};
+  double I[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (uint32_t j = b; j < e; ++j) {
+    uint32_t i = perm[j];
+    double r[3], u[3], d[3], w[3];
+    for (int k = 0; k < 3; ++k) {
+      double y = x[k * n + i] + s[k];
+      r[k] = (y - floor(y)) - rc[k];
+      u[k] = v0[k * n + i] - V[k];
+    }
+    rotate_cs(ca, sa, omc, ax, u, d);
+    for (int k = 0; k < 3; ++k) w[k] = u[k] - d[k];
+    dL[0] = dL[0] + m * (r[1] * w[2] - r[2] * w[1]);
+    dL[1] = dL[1] + m * (r[2] * w[0] - r[0] * w[2]);
+    dL[2] = dL[2] + m * (r[0] * w[1] - r[1] * w[0]);
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) I[3 * a + c] = I[3 * a + c] + m * ((a == c ? r2 : 0.0) - r[a] * r[c]);
+  }
+  double om[3] = {0.0, 0.0, 0.0};
+  if (nf == 2) {
+    uint32_t i1 = perm[b], i2 = perm[b + 1];
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      double y1 = x[k * n + i1] + s[k], y2 = x[k * n + i2] + s[k];
+      double dd = (y1 - floor(y1)) - (y2 - floor(y2));
+      d2 = d2 + dd * dd;
+    }
+    if (d2 > 0.0)
+      for (int k = 0; k < 3; ++k) om[k] = dL[k] / (m * d2 / 2.0);
+  } else {
+    double det = I[0] * (I[4] * I[8] - I[5] * I[7]) - I[1] * (I[3] * I[8] - I[5] * I[6]) +
+                 I[2] * (I[3] * I[7] - I[4] * I[6]);
+    if (det != 0.0) {
+      for (int k = 0; k < 3; ++k) {
+        double A[9];
+        memcpy(A, I, sizeof A);
+        for (int a = 0; a < 3; ++a) A[3 * a + k] = dL[a];
+        double dk = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                    A[2] * (A[3] * A[7] - A[4] * A[6]);
+        om[k] = dk / det;
+      }
+    }
+  }
+  for (uint32_t j = b; j < e; ++j) {
+    uint32_t i = perm[j];
+    double r[3];
+    for (int k = 0; k < 3; ++k) {
+      double y = x[k * n + i] + s[k];
+      r[k] = (y - floor(y)) - rc[k];
+    }
+    double oxr[3] = {om[1] * r[2] - om[2] * r[1], om[2] * r[0] - om[0] * r[2],
+                     om[0] * r[1] - om[1] * r[0]};
+    for (int k = 0; k < 3; ++k) v[k * n + i] = v[k * n + i] + oxr[k];
+  }
+}
+
+int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, double* v,
+                const uint32_t* perm, const uint32_t* offset, int64_t ncell, double* cell_out) {
+  if (p->amc && (p->walls || p->mbs || !x)) return -2;
+  const double m = p->mass;
+  double* v0 = NULL; /* pre-collision velocities (SRD+a) */
+  if (p->amc) {
+    v0 = (double*)malloc((size_t)3 * (size_t)(n > 0 ? n : 1) * sizeof(double));
+    memcpy(v0, v, (size_t)3 * (size_t)n * sizeof(double));
+  }
   const double ca = cos(p->alpha), sa = sin(p->alpha), omc = 1.0 - ca;
   double s[3];
   orc_shift(p, t, s);
@@ -436,6 +524,7 @@ int orc_collide(const orc_params* p, uint64_t t, int64_t n, double* v, const uin
         Kpost = Kpost + m * (kappa * up[k]) * (kappa * up[k]);
       }
     }
+    if (p->amc) amc_cell(p, s, n, x, v0, v, perm, b, e, V, ax, ca, sa, omc);
     if (co) {
       co[ORC_C_NX] = ax[0];
       co[ORC_C_NY] = ax[1];
@@ -445,6 +534,7 @@ int orc_collide(const orc_params* p, uint64_t t, int64_t n, double* v, const uin
     }
   }
 
+  free(v0);
   if (p->g[0] != 0.0 || p->g[1] != 0.0 || p->g[2] != 0.0) {
     for (int k = 0; k < 3; ++k) {
       double gh = p->g[k] * p->h;
@@ -475,7 +565,7 @@ int orc_step(const orc_params* p, uint64_t t, int64_t n, double* x, double* v, i
   int rc = orc_keys(p, t, n, x, key);
   if (rc == 0) {
     orc_sort(n, key, ncell, perm, offset);
-    orc_collide(p, t, n, v, perm, offset, ncell, NULL);
+    rc = orc_collide(p, t, n, x, v, perm, offset, ncell, NULL);
     if (key_out) memcpy(key_out, key, (size_t)n * sizeof(uint32_t));
     if (perm_out) memcpy(perm_out, perm, (size_t)n * sizeof(uint32_t));
     if (offset_out) memcpy(offset_out, offset, ((size_t)ncell + 1) * sizeof(uint32_t));

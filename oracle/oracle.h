@@ -10,6 +10,7 @@
  *   Sec. II         random shift of the cell grid  -> orc_shift
  *   Sec. II         sorting particles into cells   -> orc_keys, orc_sort
  *   Sec. II Eq.(2)  SRD rotation about random axis -> orc_collide
+ *   Sec. II Eqs.(3)-(4) angular-momentum conserving SRD+a -> orc_collide
  *   Sec. II (Thermostat) MBS scaling, Gamma law    -> orc_collide / orc_gamma
  *   Sec. II (Boundary conditions) bounce-back, phantom particles
  *   Sec. II (External fields) constant gravity
@@ -33,7 +34,8 @@ typedef struct {
   int32_t  L[3];      /* box in cells; with walls L[2] = H, the fluid height   */
   int32_t  walls;     /* 1: no-slip walls at z = 0 and z = H (bounce-back)     */
   int32_t  mbs;       /* 1: Maxwell-Boltzmann-scaling thermostat              */
-  int32_t  pad;
+  int32_t  amc;       /* 1: cell angular momentum conserved (SRD+a, Eqs. 3-4);
+                         periodic boxes without the thermostat only            */
   double   h;         /* MPC time step                                         */
   double   alpha;     /* rotation angle, radians                               */
   double   kT;        /* k_B T                                                 */
@@ -100,9 +102,10 @@ int32_t orc_phantoms(const orc_params* p, uint64_t t, uint32_t key, double fw,
 void orc_rotate(double alpha, const double n[3], const double u[3], double out[3]);
 
 /* Collision of step t on already streamed velocities v, given the sort.
- * x (post-stream positions) is only read for nothing but kept for symmetry;
- * cell_out (optional) receives ORC_CELL_STRIDE doubles per cell. */
-int orc_collide(const orc_params* p, uint64_t t, int64_t n, double* v,
+ * x (post-stream positions) is read only with p->amc (it may be NULL
+ * otherwise); cell_out (optional) receives ORC_CELL_STRIDE doubles per cell.
+ * Returns -2 for amc with walls or the thermostat (not defined here). */
+int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, double* v,
                 const uint32_t* perm, const uint32_t* offset, int64_t ncell,
                 double* cell_out);
 

@@ -47,6 +47,12 @@ MUTANTS = {
     "wall_fraction_bottom": ("    if (cz == 0) return sz;", "    if (cz == 0) return 1.0 - sz;"),
     "temperature_dof": ("nval(&K) / (3.0 * (double)(n - 1))", "nval(&K) / (3.0 * (double)n)"),
     "energy_half": ("nadd(&E, 0.5 * m * e);", "nadd(&E, m * e);"),
+    "amc_omega_sign": ("om[k] = dk / det;", "om[k] = -dk / det;"),
+    "amc_inertia_no_r2": ("(a == c ? r2 : 0.0) - r[a] * r[c]", "0.0 - r[a] * r[c]"),
+    "amc_about_corner": ("for (int k = 0; k < 3; ++k) rc[k] = rc[k] / (double)nf;",
+                         "for (int k = 0; k < 3; ++k) rc[k] = 0.0;"),
+    "amc_pair_factor": ("om[k] = dL[k] / (m * d2 / 2.0);", "om[k] = dL[k] / (m * d2);"),
+    "amc_torque_post": ("u[k] = v0[k * n + i] - V[k];", "u[k] = v[k * n + i] - V[k];"),
 }
 
 FAST_PINS = [
@@ -58,11 +64,15 @@ FAST_PINS = [
     "test_mbs_sets_cell_energy_to_drawn_value", "test_phantoms_enter_cell_sums",
     "test_phantom_count_and_velocity_laws", "test_wall_fraction_geometry",
     "test_observables_against_fsum", "test_reorder_is_gather", "test_philox_matches_rocrand",
+    "test_amc_conserves_angular_momentum", "test_amc_correction_is_rigid_rotation",
+    "test_amc_alpha_zero_is_identity", "test_amc_refused_with_walls_or_thermostat",
 ]
 
 PARAMS = {"test_keys_exact_floor": [{"walls": False}, {"walls": True}],
           "test_collision_is_rotation_of_relative_velocity": [{"mbs": False}, {"mbs": True}],
-          "test_gamma_sampler_distribution": [{"shape": 3.0}, {"shape": 13.5}]}
+          "test_gamma_sampler_distribution": [{"shape": 3.0}, {"shape": 13.5}],
+          "test_amc_conserves_angular_momentum": [{"L": (6, 6, 6), "density": 10.0},
+                                                  {"L": (8, 8, 8), "density": 1.5}]}
 
 
 @pytest.fixture(scope="module")

@@ -556,3 +556,86 @@ def test_poiseuille_profile(orc):
     assert abs(eta_fit / eta_th - 1) < 0.10
     resid = prof - A @ np.array([a, c])
     assert np.abs(resid).max() < 0.05 * vmax
+
+
+# --- SRD+a (angular-momentum-conserving variant, Eqs. 3-4) -------------------
+def _amc_parts(orc, L, density, t, seed, alpha=np.deg2rad(130.0)):
+    """Streamed state, binning and both collisions (plain SRD and SRD+a) of
+    one step; positions in the cell frame are frac(x + s) (a = 1)."""
+    p = orc.Params(L=L, density=density, seed=seed, alpha=alpha)
+    pa = orc.Params(L=L, density=density, seed=seed, alpha=alpha, amc=True)
+    x, v = synth.box_state(L, density=density, seed=seed + 100)
+    xs, vs, _ = orc.stream(p, x, v)
+    key = orc.keys(p, t, xs)
+    perm, off = orc.sort(key, p.ncells)
+    v_plain = orc.collide(p, t, vs, perm, off)
+    v_amc = orc.collide(pa, t, vs, perm, off, x=xs)
+    y = xs + orc.shift(p, t)[:, None]
+    frame = y - np.floor(y)
+    return key, off, frame, vs, v_plain, v_amc
+
+
+def _cell_L(r, v):
+    return np.cross(r.T, v.T).sum(axis=0)
+
+
+@pytest.mark.parametrize("L,density", [((6, 6, 6), 10.0), ((8, 8, 8), 1.5)])
+def test_amc_conserves_angular_momentum(orc, L, density):
+    """Eqs. 3-4: SRD+a keeps each cell's momentum and its angular momentum
+    about the cell's centre of mass; plain SRD (Eq. 2) does not.  The dilute
+    box has many cells of two and three particles."""
+    key, off, frame, vs, v_plain, v_amc = _amc_parts(orc, L, density, 3, 12)
+    sizes = np.diff(off)
+    if density < 2:
+        assert (sizes == 2).sum() > 20 and (sizes == 3).sum() > 20
+    broken = 0
+    for c in np.nonzero(sizes >= 2)[0]:
+        idx = np.nonzero(key == c)[0]
+        r = frame[:, idx] - frame[:, idx].mean(axis=1, keepdims=True)
+        scale = np.abs(vs[:, idx]).sum() * max(1.0, np.abs(r).max())
+        L0 = _cell_L(r, vs[:, idx])
+        assert np.abs(_cell_L(r, v_amc[:, idx]) - L0).max() <= 1e-12 * scale * idx.size
+        dP = np.abs(v_amc[:, idx].sum(axis=1) - vs[:, idx].sum(axis=1)).max()
+        assert dP <= 1e-14 * scale * idx.size
+        broken += np.abs(_cell_L(r, v_plain[:, idx]) - L0).max() > 1e-3
+    assert broken > 0.9 * (sizes >= 2).sum()
+
+
+def test_amc_correction_is_rigid_rotation(orc):
+    """Eqs. 3-4: SRD+a adds to the SRD result a rigid rotation omega x r_ic,
+    one omega per cell; a lone particle is left as SRD leaves it.  With the
+    conservation pin this fixes omega wherever the inertia tensor is regular."""
+    key, off, frame, vs, v_plain, v_amc = _amc_parts(orc, (6, 6, 6), 4.0, 5, 21)
+    sizes = np.diff(off)
+    for c in np.nonzero(sizes >= 1)[0]:
+        idx = np.nonzero(key == c)[0]
+        d = v_amc[:, idx] - v_plain[:, idx]
+        if idx.size == 1:
+            assert np.array_equal(d, np.zeros_like(d))
+            continue
+        r = frame[:, idx] - frame[:, idx].mean(axis=1, keepdims=True)
+        # omega x r = -[r]_x omega: stack the skew matrices and solve by least squares
+        A = np.concatenate([np.array([[0.0, rz, -ry], [-rz, 0.0, rx], [ry, -rx, 0.0]])
+                            for rx, ry, rz in r.T])
+        om, *_ = np.linalg.lstsq(A, d.T.reshape(-1), rcond=None)
+        assert np.abs(A @ om - d.T.reshape(-1)).max() <= 1e-12 * max(1.0, np.abs(d).max())
+
+
+def test_amc_alpha_zero_is_identity(orc):
+    """alpha = 0: D = 1, so the torque and omega vanish and SRD+a equals SRD."""
+    key, off, frame, vs, v_plain, v_amc = _amc_parts(orc, (4, 4, 4), 10.0, 2, 31, alpha=0.0)
+    assert np.array_equal(v_amc, v_plain)
+    np.testing.assert_allclose(v_amc, vs, rtol=0, atol=1e-14)
+
+
+def test_amc_refused_with_walls_or_thermostat(orc):
+    """SRD+a is taken to be defined for periodic boxes without the MBS
+    thermostat; the oracle refuses the other combinations and missing x."""
+    x, v = synth.box_state((4, 4, 4), seed=3)
+    perm, off = orc.sort(orc.keys(orc.Params(L=(4, 4, 4)), 0, x), 64)
+    with pytest.raises(ValueError):
+        orc.collide(orc.Params(L=(4, 4, 4), amc=True), 0, v, perm, off)
+    with pytest.raises(ValueError):
+        orc.collide(orc.Params(L=(4, 4, 4), amc=True, mbs=True), 0, v, perm, off, x=x)
+    with pytest.raises(ValueError):
+        orc.step(orc.Params(L=(4, 4, 4), amc=True, walls=True), 0, x, v)
