@@ -254,7 +254,7 @@ def collide(p: Params, t: int, v, perm, offset, cells: bool = False, x=None):
     rc = lib().orc_collide(C.byref(p.c()), t, v.shape[1], xp, _f64(v), _u32(perm),
                            _u32(offset), ncell, _f64(co) if cells else None)
     if rc != 0:
-        raise ValueError("SRD+a needs positions and is defined without walls and thermostat")
+        raise ValueError("SRD+a needs positions and is defined for periodic boxes")
     if cells:
         return v, co.reshape(ncell, CELL_STRIDE)
     return v
@@ -278,7 +278,7 @@ def step(p: Params, t: int, x, v, reorder: bool = False, binning: bool = False):
     rc = lib().orc_step(C.byref(p.c()), t, n, _f64(x), _f64(v), int(bool(reorder)),
                         _u32(key), _u32(perm), _u32(offset))
     if rc == -2:
-        raise ValueError("SRD+a is defined without walls and thermostat")
+        raise ValueError("SRD+a is defined for periodic boxes")
     if rc != 0:
         raise ValueError("position outside the box or not finite")
     if binning:

@@ -360,8 +360,9 @@ void orc_rotate(double alpha, const double n[3], const double u[3], double out[3
  * no periodic-image ambiguity.  Readings: a cell of two particles has a
  * singular I; the change of angular momentum then lies in I's range and the
  * pseudo-inverse, omega = dL / (m |r_1 - r_2|^2 / 2), is used; three or more
- * particles use I^-1 (Cramer's rule), and omega = 0 if det I = 0.  Applied for
- * periodic boxes without the thermostat only. */
+ * particles use I^-1 (Cramer's rule), and omega = 0 if det I = 0.  Periodic
+ * boxes only (phantom particles carry no positions).  With the thermostat, the
+ * scaling is applied to the corrected relative velocities (see orc_collide). */
 static void amc_cell(const orc_params* p, const double s[3], int64_t n, const double* x,
                      const double* v0, double* v, const uint32_t* perm, uint32_t b, uint32_t e,
                      const double V[3], const double ax[3], double ca, double sa, double omc) {
@@ -435,7 +436,7 @@ static void amc_cell(const orc_params* p, const double s[3], int64_t n, const do
 
 int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, double* v,
                 const uint32_t* perm, const uint32_t* offset, int64_t ncell, double* cell_out) {
-  if (p->amc && (p->walls || p->mbs || !x)) return -2;
+  if (p->amc && (p->walls || !x)) return -2;
   const double m = p->mass;
   double* v0 = NULL; /* pre-collision velocities (SRD+a) */
   if (p->amc) {
@@ -501,18 +502,23 @@ int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, dou
 
     double ax[3];
     orc_cell_axis(p, t, (uint32_t)c, ax);
-    double kappa = 1.0;
+    double kappa = 1.0, Ek = 0.0;
+    int have_ek = 0;
     if (p->mbs && K > 0.0) {
       int32_t att = 0;
       double gv = orc_cell_gamma(p, t, (uint32_t)c, 1.5 * (double)(ntot - 1), &att);
       if (att > 0) {
-        double Ek = p->kT * gv;
+        Ek = p->kT * gv;
+        have_ek = 1;
         kappa = sqrt((2.0 * Ek) / K);
         if (co) co[ORC_C_EK] = Ek;
       }
       if (co) co[ORC_C_ATTEMPTS] = (double)att;
     }
 
+    /* SRD+a: the rotation is unscaled; the thermostat scales the relative
+     * velocities after the angular-momentum correction (below) */
+    const double kr = p->amc ? 1.0 : kappa;
     double Kpost = 0.0;
     for (uint32_t j = b; j < e; ++j) {
       uint32_t i = perm[j];
@@ -520,11 +526,34 @@ int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, dou
       double up[3];
       rotate_cs(ca, sa, omc, ax, u, up);
       for (int k = 0; k < 3; ++k) {
-        v[k * n + i] = V[k] + kappa * up[k];
-        Kpost = Kpost + m * (kappa * up[k]) * (kappa * up[k]);
+        v[k * n + i] = V[k] + kr * up[k];
+        Kpost = Kpost + m * (kr * up[k]) * (kr * up[k]);
       }
     }
-    if (p->amc) amc_cell(p, s, n, x, v0, v, perm, b, e, V, ax, ca, sa, omc);
+    if (p->amc) {
+      amc_cell(p, s, n, x, v0, v, perm, b, e, V, ax, ca, sa, omc);
+      /* MBS with SRD+a: kappa sets the cell's relative kinetic energy after
+       * the corrected collision to the drawn E_k */
+      double K2 = 0.0;
+      for (uint32_t j = b; j < e; ++j) {
+        uint32_t i = perm[j];
+        for (int k = 0; k < 3; ++k) {
+          double du = v[k * n + i] - V[k];
+          K2 = K2 + m * du * du;
+        }
+      }
+      kappa = 1.0;
+      if (have_ek && K2 > 0.0) kappa = sqrt((2.0 * Ek) / K2);
+      Kpost = 0.0;
+      for (uint32_t j = b; j < e; ++j) {
+        uint32_t i = perm[j];
+        for (int k = 0; k < 3; ++k) {
+          double du = kappa * (v[k * n + i] - V[k]);
+          v[k * n + i] = V[k] + du;
+          Kpost = Kpost + m * du * du;
+        }
+      }
+    }
     if (co) {
       co[ORC_C_NX] = ax[0];
       co[ORC_C_NY] = ax[1];

@@ -35,7 +35,8 @@ typedef struct {
   int32_t  walls;     /* 1: no-slip walls at z = 0 and z = H (bounce-back)     */
   int32_t  mbs;       /* 1: Maxwell-Boltzmann-scaling thermostat              */
   int32_t  amc;       /* 1: cell angular momentum conserved (SRD+a, Eqs. 3-4);
-                         periodic boxes without the thermostat only            */
+                         periodic boxes only; with mbs the scaling follows the
+                         correction                                            */
   double   h;         /* MPC time step                                         */
   double   alpha;     /* rotation angle, radians                               */
   double   kT;        /* k_B T                                                 */
@@ -104,7 +105,7 @@ void orc_rotate(double alpha, const double n[3], const double u[3], double out[3
 /* Collision of step t on already streamed velocities v, given the sort.
  * x (post-stream positions) is read only with p->amc (it may be NULL
  * otherwise); cell_out (optional) receives ORC_CELL_STRIDE doubles per cell.
- * Returns -2 for amc with walls or the thermostat (not defined here). */
+ * Returns -2 for amc with walls or without x. */
 int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, double* v,
                 const uint32_t* perm, const uint32_t* offset, int64_t ncell,
                 double* cell_out);

@@ -53,6 +53,9 @@ MUTANTS = {
                          "for (int k = 0; k < 3; ++k) rc[k] = 0.0;"),
     "amc_pair_factor": ("om[k] = dL[k] / (m * d2 / 2.0);", "om[k] = dL[k] / (m * d2);"),
     "amc_torque_post": ("u[k] = v0[k * n + i] - V[k];", "u[k] = v[k * n + i] - V[k];"),
+    "amc_mbs_pre_energy": ("if (have_ek && K2 > 0.0) kappa = sqrt((2.0 * Ek) / K2);",
+                           "if (have_ek && K2 > 0.0) kappa = sqrt((2.0 * Ek) / K);"),
+    "amc_mbs_scaled_twice": ("const double kr = p->amc ? 1.0 : kappa;", "const double kr = kappa;"),
 }
 
 FAST_PINS = [
@@ -65,7 +68,7 @@ FAST_PINS = [
     "test_phantom_count_and_velocity_laws", "test_wall_fraction_geometry",
     "test_observables_against_fsum", "test_reorder_is_gather", "test_philox_matches_rocrand",
     "test_amc_conserves_angular_momentum", "test_amc_correction_is_rigid_rotation",
-    "test_amc_alpha_zero_is_identity", "test_amc_refused_with_walls_or_thermostat",
+    "test_amc_alpha_zero_is_identity", "test_amc_refused_with_walls", "test_amc_with_thermostat",
 ]
 
 PARAMS = {"test_keys_exact_floor": [{"walls": False}, {"walls": True}],

@@ -628,14 +628,48 @@ def test_amc_alpha_zero_is_identity(orc):
     np.testing.assert_allclose(v_amc, vs, rtol=0, atol=1e-14)
 
 
-def test_amc_refused_with_walls_or_thermostat(orc):
-    """SRD+a is taken to be defined for periodic boxes without the MBS
-    thermostat; the oracle refuses the other combinations and missing x."""
+def test_amc_refused_with_walls(orc):
+    """SRD+a is taken to be defined for periodic boxes (phantom particles carry
+    no positions); the oracle refuses walls and a missing x."""
     x, v = synth.box_state((4, 4, 4), seed=3)
     perm, off = orc.sort(orc.keys(orc.Params(L=(4, 4, 4)), 0, x), 64)
     with pytest.raises(ValueError):
         orc.collide(orc.Params(L=(4, 4, 4), amc=True), 0, v, perm, off)
     with pytest.raises(ValueError):
-        orc.collide(orc.Params(L=(4, 4, 4), amc=True, mbs=True), 0, v, perm, off, x=x)
-    with pytest.raises(ValueError):
         orc.step(orc.Params(L=(4, 4, 4), amc=True, walls=True), 0, x, v)
+
+
+def test_amc_with_thermostat(orc):
+    """SRD+a with MBS: per cell, the corrected relative velocities of SRD+a
+    scaled by one factor kappa whose result has relative kinetic energy equal
+    to the drawn E_k (Gamma(3(N_c-1)/2, kT) law); momentum is conserved and
+    the angular momentum about the centre of mass is scaled by kappa."""
+    L = (10, 10, 10)
+    t = 4
+    pa = orc.Params(L=L, amc=True, seed=17, kT=1.3)
+    pm = orc.Params(L=L, amc=True, mbs=True, seed=17, kT=1.3)
+    x, v = synth.box_state(L, seed=91, kT=0.7)
+    xs, vs, _ = orc.stream(pa, x, v)
+    key = orc.keys(pa, t, xs)
+    perm, off = orc.sort(key, pa.ncells)
+    va = orc.collide(pa, t, vs, perm, off, x=xs)
+    vm, cells = orc.collide(pm, t, vs, perm, off, cells=True, x=xs)
+    y = xs + orc.shift(pa, t)[:, None]
+    fr = y - np.floor(y)
+    sel = np.nonzero(cells[:, 0] >= 2)[0]
+    for c in sel:
+        idx = perm[off[c]:off[c + 1]]
+        V = cells[c, 2:5][:, None]
+        scale = np.abs(vs[:, idx]).sum()
+        assert np.abs(vm[:, idx].sum(axis=1) - vs[:, idx].sum(axis=1)).max() <= 1e-14 * scale
+        da, dm = va[:, idx] - V, vm[:, idx] - V
+        kappa = math.sqrt(2 * cells[c, 10] / (da ** 2).sum())
+        np.testing.assert_allclose(dm, kappa * da, rtol=0, atol=1e-13 * np.abs(dm).max())
+        assert abs((dm ** 2).sum() - 2 * cells[c, 10]) <= 1e-12 * cells[c, 10]
+        r = fr[:, idx] - fr[:, idx].mean(axis=1, keepdims=True)
+        L0 = _cell_L(r, vs[:, idx])
+        np.testing.assert_allclose(_cell_L(r, vm[:, idx]), kappa * L0, rtol=0,
+                                   atol=1e-12 * scale)
+    np.testing.assert_allclose(cells[sel, 15], 2 * cells[sel, 10], rtol=1e-12)
+    u = stats.gamma.cdf(cells[sel, 10] / pm.kT, 1.5 * (cells[sel, 0] - 1))
+    assert stats.kstest(u, "uniform").pvalue > 1e-3
