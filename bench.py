@@ -11,8 +11,9 @@ timed region; 200 steps by default).  The same line carries:
                  the HBM bytes per launch from rocprofv3 counter runs of this
                  same command, when they were taken on the current kernels;
   forms        : FP32 and split-FP32 on the same box, FP64 stored in cell
-                 order after every step, and the batched ensemble of 64
-                 uneven boxes (graph replay);
+                 order after every step, the batched ensemble of 64
+                 uneven boxes (graph replay), and the angular-momentum-
+                 conserving collision SRD+a in FP64 and split-FP32;
   cpu_baseline : the single-threaded CPU oracle on a bounded sample.
 --copy-probe-gib G adds one device-to-device copy of G GiB before the run: the
 counter runs use it to scale FETCH_SIZE / WRITE_SIZE to bytes.
@@ -224,7 +225,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--forms", default="fp32,split,fp64_sorted_every_step,batched",
+    ap.add_argument("--forms", default="fp32,split,fp64_sorted_every_step,batched,amc,amc_split",
                     help="extra entries besides the FP64 headline (comma list, or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=500)
@@ -323,6 +324,25 @@ def main():
                     "collide_ms": c2,
                     "collide_achieved_GBs": n2 * 2 * STATE_BYTES["fp64"] / (c2 * 1e-3) / 1e9}
                 print(f"[fp64 R=1 C2] {w2 * 1e3 / args.steps:.3f} ms/step collide {c2:.3f} ms",
+                      file=sys.stderr)
+            elif form in ("amc", "amc_split"):
+                fm = "fp64" if form == "amc" else "split"
+                abox = dict(box, mbs=False, amc=True)
+                n2, w2, k2, o2 = run_box(mpc, torch, abox, fm, R, args.steps, args.warmup)
+                v2 = n2 * args.steps / w2
+                c2 = k2.collide_ms / max(1, k2.collide_launches)
+                forms[form] = {
+                    "workload": f"same 256^3 box, {fm}, collision SRD+a (angular momentum "
+                                f"conserving, no thermostat), reorder every {R} steps",
+                    "value": v2, "unit": "particle-steps/s",
+                    "ms_per_step": w2 * 1e3 / args.steps,
+                    "hbm_roofline_frac_step": v2 * 2 * STATE_BYTES[fm] / (HBM_PEAK_GBS * 1e9),
+                    "collide_ms": c2,
+                    "collide_achieved_GBs": n2 * 2 * STATE_BYTES[fm] / (c2 * 1e-3) / 1e9,
+                    "collide_roofline_frac": n2 * 2 * STATE_BYTES[fm] / (c2 * 1e-3) / 1e9
+                    / HBM_PEAK_GBS,
+                    "launch": run_box.last_tiling, "T_end": o2["T"]}
+                print(f"[{form} C2] {w2 * 1e3 / args.steps:.3f} ms/step collide {c2:.3f} ms",
                       file=sys.stderr)
             elif form == "c3":
                 forms["c3"] = run_c3(mpc, torch, synth, args.c3_steps)

@@ -60,9 +60,17 @@ typedef enum {
 /* Feature flags (identical for all boxes of one handle). */
 enum {
   MPC_MBS = 1u,     /* Maxwell-Boltzmann scaling thermostat (Sec. II, Thermostat)     */
-  MPC_WALLS_Z = 2u  /* no-slip walls at z = 0 and z = L[2] = H: bounce-back streaming
+  MPC_WALLS_Z = 2u, /* no-slip walls at z = 0 and z = L[2] = H: bounce-back streaming
                        and phantom particles in wall-cut cells (Sec. II, Boundary
                        conditions); x and y stay periodic                              */
+  MPC_AMC = 4u      /* angular-momentum-conserving collision SRD+a (Sec. II, Eqs. 3-4):
+                       v_i' = v_cm + D u_i + omega x r_ic with omega = I^-1 dL, where
+                       r_ic is the position relative to the cell's centre of mass in
+                       the shifted cell's frame, frac(x/a + s), I the inertia tensor
+                       and dL = m sum_i r_ic x (u_i - D u_i).  A cell of two uses the
+                       pseudo-inverse of its singular I, omega = dL / (m |r_12|^2 / 2);
+                       det I = 0 gives omega = 0.  Periodic boxes only and not with
+                       MPC_MBS: combined with MPC_MBS or MPC_WALLS_Z -> MPC_EINVAL   */
 };
 
 /* Error codes. */
@@ -85,7 +93,7 @@ enum {
 typedef struct {
   int32_t  L[3];          /* box in cells; with MPC_WALLS_Z, L[2] = H                     */
   int32_t  form;          /* mpc_form (same for all boxes)                                 */
-  uint32_t flags;         /* MPC_MBS | MPC_WALLS_Z (same for all boxes)                    */
+  uint32_t flags;         /* MPC_MBS | MPC_WALLS_Z, or MPC_AMC (same for all boxes)       */
   int32_t  reorder_every; /* R: renumber particles in (cell, index) order after every
                              R-th step; 0 = never (same for all boxes)                    */
   double   a;             /* cell size, > 0                                                */

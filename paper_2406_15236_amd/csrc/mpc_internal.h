@@ -113,7 +113,7 @@ struct Dev {           // device pointers carved from the workspace
 struct Launch {
   int form;
   int round_phantoms;      // split form: phantom velocities rounded to FP32
-  int walls, mbs;          // feature flags (identical for all boxes)
+  int walls, mbs, amc;     // feature flags (identical for all boxes)
   uint32_t nbox;
   uint64_t ntot, ctot;     // particles, cells over all boxes
   uint32_t ntiles, npblocks, nscan;
@@ -138,6 +138,6 @@ hipError_t launch_obs_pass1(const Dev& d, const Launch& l);
 hipError_t launch_obs_pass2(const Dev& d, const Launch& l, const double* vmean_dev);
 hipError_t launch_remove_mean(const Dev& d, const Launch& l, const double* vmean_dev);
 hipError_t launch_canon_perm(const Dev& d, const Launch& l, const uint32_t* ids);
-hipError_t collide_occupancy(int form, int walls, int mbs, int* blocks_per_cu);
+hipError_t collide_occupancy(int form, int walls, int mbs, int amc, int* blocks_per_cu);
 
 }  // namespace mpc

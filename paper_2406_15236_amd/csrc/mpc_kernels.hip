@@ -952,14 +952,45 @@ struct CellLdsSplit {
   float R[9];    // kappa * rotation matrix, row major
   float coll;    // 0 = the cell does not collide
 };
-template <int F>
+// SRD+a (Eqs. 3-4) adds the centre of mass in the cell frame and the angular
+// velocity of the correction omega x r_ic.
+struct CellLdsAmc : CellLds {
+  double rc[3];
+  double om[3];
+};
+struct CellLdsSplitAmc : CellLdsSplit {
+  float rc[3];
+  float om[3];
+};
+template <int F, bool A>
 struct CellRec {
   using T = CellLds;
 };
 template <>
-struct CellRec<kFormSplit> {
+struct CellRec<kFormF64, true> {
+  using T = CellLdsAmc;
+};
+template <>
+struct CellRec<kFormF32, true> {
+  using T = CellLdsAmc;
+};
+template <>
+struct CellRec<kFormSplit, false> {
   using T = CellLdsSplit;
 };
+template <>
+struct CellRec<kFormSplit, true> {
+  using T = CellLdsSplitAmc;
+};
+
+// Position of a particle in the frame of its (shifted) cell, frac(x + s),
+// from the stored coordinate (FP64 and FP32 forms: x; split form: the offset,
+// whose cell index is an integer and drops out).  Exact for the FP32 forms.
+template <typename X>
+__device__ __forceinline__ double frame_pos(X x, double s) {
+  const double y = (double)x + s;
+  return y - floor(y);
+}
 
 // Rotation by alpha about n (Eq. 2): R u = cos(a) u + sin(a) n x u +
 // (1 - cos(a)) (n . u) n.
@@ -982,13 +1013,17 @@ __device__ __forceinline__ void rotate(T ca, T sa, T omc, const T (&n)[3], const
 __device__ __forceinline__ double pair_xor(double x) { return __shfl_xor(x, 1, 64); }
 __device__ __forceinline__ float pair_xor(float x) { return __shfl_xor(x, 1, 64); }
 
-template <int F, bool W, bool M>
+template <int F, bool W, bool M, bool A>
 __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd,
                           const PhantomSums* __restrict__ ph,
                           const typename Form<F>::Vs* __restrict__ sv0,
                           const typename Form<F>::Vs* __restrict__ sv1,
-                          const typename Form<F>::Vs* __restrict__ sv2, uint32_t b, uint32_t e,
-                          uint32_t half, bool valid, typename CellRec<F>::T* out) {
+                          const typename Form<F>::Vs* __restrict__ sv2,
+                          const typename Form<F>::Xs* __restrict__ sx0,
+                          const typename Form<F>::Xs* __restrict__ sx1,
+                          const typename Form<F>::Xs* __restrict__ sx2, const double (&s)[3],
+                          uint32_t b, uint32_t e, uint32_t half, bool valid,
+                          typename CellRec<F, A>::T* out) {
   const uint32_t nf = valid ? e - b : 0u;
   const uint32_t mid = b + (nf + 1) / 2;
   const uint32_t qb = half ? mid : b, qe = valid ? (half ? e : mid) : b;
@@ -1085,9 +1120,78 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
     }
     if (cd.Ek > 0.0 && K > 0.0) kappa = sqrt((2.0 * cd.Ek) / K);
   }
+  // SRD+a (Eqs. 3-4, periodic boxes without thermostat): omega = I^-1 dL with
+  // dL = sum r_ic x (u_i - D u_i) and I the inertia tensor, both about the
+  // centre of mass of the cell-frame positions (the mass m cancels).  A pair
+  // uses the pseudo-inverse of its singular I (omega = dL / (tr I / 2), since
+  // tr I = |r_1 - r_2|^2), three or more Cramer's rule, and det I = 0 gives
+  // omega = 0.  Both lanes of the pair build identical totals.
+  double rc[3] = {0.0, 0.0, 0.0}, om[3] = {0.0, 0.0, 0.0};
+  if constexpr (A) {
+    for (uint32_t q = qb; q < qe; ++q) {
+      rc[0] = rc[0] + frame_pos(sx0[q], s[0]);
+      rc[1] = rc[1] + frame_pos(sx1[q], s[1]);
+      rc[2] = rc[2] + frame_pos(sx2[q], s[2]);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double o = pair_xor(rc[k]);
+      rc[k] = (half ? o + rc[k] : rc[k] + o) / (double)(nf ? nf : 1u);
+    }
+    // dL[0..2]; I: xx, yy, zz, xy, xz, yz
+    double a9[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const double n[3] = {cd.n[0], cd.n[1], cd.n[2]};
+    for (uint32_t q = qb; q < qe; ++q) {
+      const double r[3] = {frame_pos(sx0[q], s[0]) - rc[0], frame_pos(sx1[q], s[1]) - rc[1],
+                           frame_pos(sx2[q], s[2]) - rc[2]};
+      const double u[3] = {(double)sv0[q] - V[0], (double)sv1[q] - V[1], (double)sv2[q] - V[2]};
+      double du[3];
+      rotate<double>(B.ca, B.sa, B.omc, n, u, du);
+      const double w[3] = {u[0] - du[0], u[1] - du[1], u[2] - du[2]};
+      a9[0] = a9[0] + (r[1] * w[2] - r[2] * w[1]);
+      a9[1] = a9[1] + (r[2] * w[0] - r[0] * w[2]);
+      a9[2] = a9[2] + (r[0] * w[1] - r[1] * w[0]);
+      a9[3] = a9[3] + (r[1] * r[1] + r[2] * r[2]);
+      a9[4] = a9[4] + (r[0] * r[0] + r[2] * r[2]);
+      a9[5] = a9[5] + (r[0] * r[0] + r[1] * r[1]);
+      a9[6] = a9[6] - r[0] * r[1];
+      a9[7] = a9[7] - r[0] * r[2];
+      a9[8] = a9[8] - r[1] * r[2];
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double o = pair_xor(a9[k]);
+      a9[k] = half ? o + a9[k] : a9[k] + o;
+    }
+    const double xx = a9[3], yy = a9[4], zz = a9[5], xy = a9[6], xz = a9[7], yz = a9[8];
+    if (nf == 2) {
+      const double hm = 0.5 * (xx + yy + zz);
+      if (hm > 0.0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) om[k] = a9[k] / hm;
+      }
+    } else if (nf >= 3) {
+      // adjugate of the symmetric I
+      const double c00 = yy * zz - yz * yz, c01 = xz * yz - xy * zz, c02 = xy * yz - yy * xz;
+      const double c11 = xx * zz - xz * xz, c12 = xy * xz - xx * yz, c22 = xx * yy - xy * xy;
+      const double det = xx * c00 + xy * c01 + xz * c02;
+      if (det != 0.0) {
+        om[0] = (c00 * a9[0] + c01 * a9[1] + c02 * a9[2]) / det;
+        om[1] = (c01 * a9[0] + c11 * a9[1] + c12 * a9[2]) / det;
+        om[2] = (c02 * a9[0] + c12 * a9[1] + c22 * a9[2]) / det;
+      }
+    }
+  }
   if (!valid || half) return;
   // cells that do not collide keep v exactly (kappa = 0 / coll = 0 marks them)
   const bool coll = nf > 0 && ntot >= 2;
+  if constexpr (A) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      out->rc[k] = rc[k];
+      out->om[k] = coll ? om[k] : 0.0;
+    }
+  }
   if constexpr (F == kFormSplit) {
     const double n[3] = {cd.n[0], cd.n[1], cd.n[2]};
     const double ca = B.ca, sa = B.sa, omc = B.omc;
@@ -1133,8 +1237,8 @@ struct TileWalk {
   }
 };
 
-template <int F, bool W, bool M>
-__global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu(W ? 2 : 3)))
+template <int F, bool W, bool M, bool A>
+__global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu((W || A) ? 2 : 3)))
 void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   using Fm = Form<F>;
   using Vs = typename Fm::Vs;
@@ -1152,7 +1256,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   __shared__ Vs s_v[3][kTileCap];        // streamed velocities, canonical order
   __shared__ Xs s_x[3][kTileCap];        // streamed positions (offsets), canonical order
   __shared__ uint32_t s_c[Fm::kHasCell ? kTileCap : 1];
-  __shared__ typename CellRec<F>::T s_cell[kTileMaxCells];
+  __shared__ typename CellRec<F, A>::T s_cell[kTileMaxCells];
   __shared__ double s_sh[6];
   // next-step window of the tile: cells x0-1 .. x0+nc of the rows (y0 +- 1,
   // z0 +- 1), plus one entry for particles that leave it; per pass: counts,
@@ -1390,8 +1494,11 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             cd.Ek = 0.0;
           }
         }
-        cell_work<F, W, M>(B, lkey0 + c, s_sh[2], cd, W ? d.phs + T.c0 + (valid ? c : 0u) : nullptr,
-                           s_v[0], s_v[1], s_v[2], b, e, lane & 1u, valid, &s_cell[j]);
+        const double s_t[3] = {s_sh[0], s_sh[1], s_sh[2]};
+        cell_work<F, W, M, A>(B, lkey0 + c, s_sh[2], cd,
+                              W ? d.phs + T.c0 + (valid ? c : 0u) : nullptr, s_v[0], s_v[1],
+                              s_v[2], s_x[0], s_x[1], s_x[2], s_t, b, e, lane & 1u, valid,
+                              &s_cell[j]);
       }
       wave_sync();
 
@@ -1418,6 +1525,14 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
 #pragma unroll
               for (int a = 0; a < 3; ++a)
                 v.v[a] = C.V[a] + fmaf(C.R[3 * a], u[0], fmaf(C.R[3 * a + 1], u[1], C.R[3 * a + 2] * u[2]));
+              if constexpr (A) {
+                const float r[3] = {(float)frame_pos(s_x[0][q], s_sh[0]) - C.rc[0],
+                                    (float)frame_pos(s_x[1][q], s_sh[1]) - C.rc[1],
+                                    (float)frame_pos(s_x[2][q], s_sh[2]) - C.rc[2]};
+                v.v[0] = v.v[0] + (C.om[1] * r[2] - C.om[2] * r[1]);
+                v.v[1] = v.v[1] + (C.om[2] * r[0] - C.om[0] * r[2]);
+                v.v[2] = v.v[2] + (C.om[0] * r[1] - C.om[1] * r[0]);
+              }
             }
             if (B.grav) {
 #pragma unroll
@@ -1432,6 +1547,14 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
               rotate<double>(B.ca, B.sa, B.omc, nd, u, r);
 #pragma unroll
               for (int a = 0; a < 3; ++a) w[a] = C.V[a] + C.kappa * r[a];
+              if constexpr (A) {
+                const double rr[3] = {frame_pos(s_x[0][q], s_sh[0]) - C.rc[0],
+                                      frame_pos(s_x[1][q], s_sh[1]) - C.rc[1],
+                                      frame_pos(s_x[2][q], s_sh[2]) - C.rc[2]};
+                w[0] = w[0] + (C.om[1] * rr[2] - C.om[2] * rr[1]);
+                w[1] = w[1] + (C.om[2] * rr[0] - C.om[0] * rr[2]);
+                w[2] = w[2] + (C.om[0] * rr[1] - C.om[1] * rr[0]);
+              }
             }
             if (B.grav) {
 #pragma unroll
@@ -1564,12 +1687,20 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   if (err) atomicOr(&d.ctrl->err, err);
 }
 
-template <int F, bool W, bool M>
+template <int F, bool W, bool M, bool A = false>
 static hipError_t occ_of(int* n) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_collide<F, W, M>, kCollideThreads, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_collide<F, W, M, A>, kCollideThreads, 0);
 }
 
-hipError_t collide_occupancy(int form, int walls, int mbs, int* blocks_per_cu) {
+hipError_t collide_occupancy(int form, int walls, int mbs, int amc, int* blocks_per_cu) {
+  if (amc) {
+    if (walls || mbs) return hipErrorInvalidValue;
+    switch (form) {
+      case kFormF64: return occ_of<kFormF64, false, false, true>(blocks_per_cu);
+      case kFormF32: return occ_of<kFormF32, false, false, true>(blocks_per_cu);
+      default: return occ_of<kFormSplit, false, false, true>(blocks_per_cu);
+    }
+  }
   const int sel = form * 4 + (walls ? 2 : 0) + (mbs ? 1 : 0);
   switch (sel) {
     case 0: return occ_of<kFormF64, false, false>(blocks_per_cu);
@@ -1847,9 +1978,26 @@ hipError_t launch_collide(const Dev& d, const Launch& l) {
   const dim3 g(l.collide_grid), b(kCollideThreads);
   const uint32_t nt = l.ntiles;
   const int xr = l.xcd_remap;
+  if (l.amc) {
+    if (l.walls || l.mbs) return hipErrorInvalidValue;
+    switch (l.form) {
+      case kFormF64:
+        hipLaunchKernelGGL((k_collide<kFormF64, false, false, true>), g, b, 0, l.stream, d, nt, xr);
+        break;
+      case kFormF32:
+        hipLaunchKernelGGL((k_collide<kFormF32, false, false, true>), g, b, 0, l.stream, d, nt, xr);
+        break;
+      case kFormSplit:
+        hipLaunchKernelGGL((k_collide<kFormSplit, false, false, true>), g, b, 0, l.stream, d, nt,
+                           xr);
+        break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (l.form * 4 + (l.walls ? 2 : 0) + (l.mbs ? 1 : 0)) {
 #define MPC_COLLIDE_CASE(n, F, W, M) \
-  case n: hipLaunchKernelGGL((k_collide<F, W, M>), g, b, 0, l.stream, d, nt, xr); break;
+  case n: hipLaunchKernelGGL((k_collide<F, W, M, false>), g, b, 0, l.stream, d, nt, xr); break;
     MPC_COLLIDE_CASE(0, kFormF64, false, false)
     MPC_COLLIDE_CASE(1, kFormF64, false, true)
     MPC_COLLIDE_CASE(2, kFormF64, true, false)

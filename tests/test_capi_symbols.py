@@ -64,3 +64,21 @@ def test_workspace_planning_and_validation_on_host():
     boxes = synth.batch_boxes(4, lmin=16, lmax=20)
     tot = m.workspace_bytes([m.make_params(b) for b in boxes])
     assert tot > max(m.workspace_bytes(m.make_params(b)) for b in boxes)
+
+
+def test_amc_flag_validation_on_host():
+    """SRD+a (MPC_AMC) is accepted for periodic boxes without the thermostat
+    and refused with MPC_MBS or MPC_WALLS_Z."""
+    import paper_2406_15236_amd as m
+    import synth
+    if not os.path.exists(m.LIB):
+        pytest.skip("library not built")
+    c1 = synth.config("C1")
+    assert m.workspace_bytes(m.make_params(dict(c1, amc=True))) > 0
+    for kw in ({"mbs": True}, {"walls": True}):
+        with pytest.raises(m.MPCError) as e:
+            m.workspace_bytes(m.make_params(dict(c1, amc=True, **kw)))
+        assert e.value.code == m.EINVAL
+    with pytest.raises(m.MPCError) as e:
+        m.workspace_bytes(m.make_params(c1, flags=8))
+    assert e.value.code == m.EINVAL
