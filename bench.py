@@ -327,13 +327,13 @@ def main():
                       file=sys.stderr)
             elif form in ("amc", "amc_split"):
                 fm = "fp64" if form == "amc" else "split"
-                abox = dict(box, mbs=False, amc=True)
+                abox = dict(box, amc=True)
                 n2, w2, k2, o2 = run_box(mpc, torch, abox, fm, R, args.steps, args.warmup)
                 v2 = n2 * args.steps / w2
                 c2 = k2.collide_ms / max(1, k2.collide_launches)
                 forms[form] = {
-                    "workload": f"same 256^3 box, {fm}, collision SRD+a (angular momentum "
-                                f"conserving, no thermostat), reorder every {R} steps",
+                    "workload": f"same 256^3 box and thermostat, {fm}, collision SRD+a "
+                                f"(angular momentum conserving), reorder every {R} steps",
                     "value": v2, "unit": "particle-steps/s",
                     "ms_per_step": w2 * 1e3 / args.steps,
                     "hbm_roofline_frac_step": v2 * 2 * STATE_BYTES[fm] / (HBM_PEAK_GBS * 1e9),

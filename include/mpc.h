@@ -69,8 +69,11 @@ enum {
                        the shifted cell's frame, frac(x/a + s), I the inertia tensor
                        and dL = m sum_i r_ic x (u_i - D u_i).  A cell of two uses the
                        pseudo-inverse of its singular I, omega = dL / (m |r_12|^2 / 2);
-                       det I = 0 gives omega = 0.  Periodic boxes only and not with
-                       MPC_MBS: combined with MPC_MBS or MPC_WALLS_Z -> MPC_EINVAL   */
+                       det I = 0 gives omega = 0.  With MPC_MBS the rotation is not
+                       scaled; kappa scales the corrected relative velocities
+                       D u_i + omega x r_ic so that their kinetic energy equals the
+                       drawn E_k (angular momentum is then scaled by kappa).
+                       Periodic boxes only: with MPC_WALLS_Z -> MPC_EINVAL           */
 };
 
 /* Error codes. */
@@ -93,7 +96,7 @@ enum {
 typedef struct {
   int32_t  L[3];          /* box in cells; with MPC_WALLS_Z, L[2] = H                     */
   int32_t  form;          /* mpc_form (same for all boxes)                                 */
-  uint32_t flags;         /* MPC_MBS | MPC_WALLS_Z, or MPC_AMC (same for all boxes)       */
+  uint32_t flags;         /* MPC_MBS | MPC_WALLS_Z | MPC_AMC (same for all boxes)         */
   int32_t  reorder_every; /* R: renumber particles in (cell, index) order after every
                              R-th step; 0 = never (same for all boxes)                    */
   double   a;             /* cell size, > 0                                                */

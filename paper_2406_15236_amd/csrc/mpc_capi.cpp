@@ -59,8 +59,8 @@ int validate(const mpc_params* p, int32_t nbox, std::string* why) {
     };
     if (q.form < MPC_FP64 || q.form > MPC_SPLIT32) return bad("unknown form");
     if (q.flags & ~(uint32_t)(MPC_MBS | MPC_WALLS_Z | MPC_AMC)) return bad("unknown flags");
-    if ((q.flags & MPC_AMC) && (q.flags & (MPC_MBS | MPC_WALLS_Z)))
-      return bad("MPC_AMC is defined for periodic boxes without the thermostat");
+    if ((q.flags & MPC_AMC) && (q.flags & MPC_WALLS_Z))
+      return bad("MPC_AMC is defined for periodic boxes (no MPC_WALLS_Z)");
     if (q.form != p[0].form || q.flags != p[0].flags || q.reorder_every != p[0].reorder_every)
       return bad("form, flags and reorder_every must be equal for all boxes");
     if (q.reorder_every < 0) return bad("reorder_every < 0");

@@ -1101,9 +1101,8 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
     V[1] = P[1] / Mtot;
     V[2] = P[2] / Mtot;
   }
-  double kappa = 1.0;
+  double kappa = 1.0, K = 0.0;
   if (M) {
-    double K = 0.0;
 #pragma unroll 4
     for (uint32_t q = qb; q < qe; ++q) {
       const double dx = (double)sv0[q] - V[0], dy = (double)sv1[q] - V[1],
@@ -1120,7 +1119,7 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
     }
     if (cd.Ek > 0.0 && K > 0.0) kappa = sqrt((2.0 * cd.Ek) / K);
   }
-  // SRD+a (Eqs. 3-4, periodic boxes without thermostat): omega = I^-1 dL with
+  // SRD+a (Eqs. 3-4, periodic boxes): omega = I^-1 dL with
   // dL = sum r_ic x (u_i - D u_i) and I the inertia tensor, both about the
   // centre of mass of the cell-frame positions (the mass m cancels).  A pair
   // uses the pseudo-inverse of its singular I (omega = dL / (tr I / 2), since
@@ -1138,8 +1137,12 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
       const double o = pair_xor(rc[k]);
       rc[k] = (half ? o + rc[k] : rc[k] + o) / (double)(nf ? nf : 1u);
     }
-    // dL[0..2]; I: xx, yy, zz, xy, xz, yz
-    double a9[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // dL[0..2]; I: xx, yy, zz, xy, xz, yz; with the thermostat also the
+    // angular momentum L0 = sum r_ic x u_i
+    constexpr int NA = M ? 12 : 9;
+    double a9[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) a9[k] = 0.0;
     const double n[3] = {cd.n[0], cd.n[1], cd.n[2]};
     for (uint32_t q = qb; q < qe; ++q) {
       const double r[3] = {frame_pos(sx0[q], s[0]) - rc[0], frame_pos(sx1[q], s[1]) - rc[1],
@@ -1157,9 +1160,14 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
       a9[6] = a9[6] - r[0] * r[1];
       a9[7] = a9[7] - r[0] * r[2];
       a9[8] = a9[8] - r[1] * r[2];
+      if constexpr (M) {
+        a9[9] = a9[9] + (r[1] * u[2] - r[2] * u[1]);
+        a9[10] = a9[10] + (r[2] * u[0] - r[0] * u[2]);
+        a9[11] = a9[11] + (r[0] * u[1] - r[1] * u[0]);
+      }
     }
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
+    for (int k = 0; k < NA; ++k) {
       const double o = pair_xor(a9[k]);
       a9[k] = half ? o + a9[k] : a9[k] + o;
     }
@@ -1180,6 +1188,27 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
         om[1] = (c01 * a9[0] + c11 * a9[1] + c12 * a9[2]) / det;
         om[2] = (c02 * a9[0] + c12 * a9[1] + c22 * a9[2]) / det;
       }
+    }
+    if constexpr (M) {
+      // the thermostat scales the corrected relative velocities D u_i +
+      // omega x r_ic to the drawn energy; their kinetic energy is
+      // K + m (2 omega . (L0 - dL) + omega . I omega), K that of the u_i
+      kappa = 1.0;
+      if (cd.Ek > 0.0) {
+        const double Io[3] = {xx * om[0] + xy * om[1] + xz * om[2],
+                              xy * om[0] + yy * om[1] + yz * om[2],
+                              xz * om[0] + yz * om[1] + zz * om[2]};
+        double cr = 0.0, q = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          cr = cr + om[k] * (a9[9 + k] - a9[k]);
+          q = q + om[k] * Io[k];
+        }
+        const double K2 = K + m * (2.0 * cr + q);
+        if (K2 > 0.0) kappa = sqrt((2.0 * cd.Ek) / K2);
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) om[k] = kappa * om[k];
     }
   }
   if (!valid || half) return;
@@ -1694,11 +1723,14 @@ static hipError_t occ_of(int* n) {
 
 hipError_t collide_occupancy(int form, int walls, int mbs, int amc, int* blocks_per_cu) {
   if (amc) {
-    if (walls || mbs) return hipErrorInvalidValue;
-    switch (form) {
-      case kFormF64: return occ_of<kFormF64, false, false, true>(blocks_per_cu);
-      case kFormF32: return occ_of<kFormF32, false, false, true>(blocks_per_cu);
-      default: return occ_of<kFormSplit, false, false, true>(blocks_per_cu);
+    if (walls) return hipErrorInvalidValue;
+    switch (form * 2 + (mbs ? 1 : 0)) {
+      case 0: return occ_of<kFormF64, false, false, true>(blocks_per_cu);
+      case 1: return occ_of<kFormF64, false, true, true>(blocks_per_cu);
+      case 2: return occ_of<kFormF32, false, false, true>(blocks_per_cu);
+      case 3: return occ_of<kFormF32, false, true, true>(blocks_per_cu);
+      case 4: return occ_of<kFormSplit, false, false, true>(blocks_per_cu);
+      default: return occ_of<kFormSplit, false, true, true>(blocks_per_cu);
     }
   }
   const int sel = form * 4 + (walls ? 2 : 0) + (mbs ? 1 : 0);
@@ -1979,18 +2011,17 @@ hipError_t launch_collide(const Dev& d, const Launch& l) {
   const uint32_t nt = l.ntiles;
   const int xr = l.xcd_remap;
   if (l.amc) {
-    if (l.walls || l.mbs) return hipErrorInvalidValue;
-    switch (l.form) {
-      case kFormF64:
-        hipLaunchKernelGGL((k_collide<kFormF64, false, false, true>), g, b, 0, l.stream, d, nt, xr);
-        break;
-      case kFormF32:
-        hipLaunchKernelGGL((k_collide<kFormF32, false, false, true>), g, b, 0, l.stream, d, nt, xr);
-        break;
-      case kFormSplit:
-        hipLaunchKernelGGL((k_collide<kFormSplit, false, false, true>), g, b, 0, l.stream, d, nt,
-                           xr);
-        break;
+    if (l.walls) return hipErrorInvalidValue;
+    switch (l.form * 2 + (l.mbs ? 1 : 0)) {
+#define MPC_AMC_CASE(n, F, M) \
+  case n: hipLaunchKernelGGL((k_collide<F, false, M, true>), g, b, 0, l.stream, d, nt, xr); break;
+      MPC_AMC_CASE(0, kFormF64, false)
+      MPC_AMC_CASE(1, kFormF64, true)
+      MPC_AMC_CASE(2, kFormF32, false)
+      MPC_AMC_CASE(3, kFormF32, true)
+      MPC_AMC_CASE(4, kFormSplit, false)
+      MPC_AMC_CASE(5, kFormSplit, true)
+#undef MPC_AMC_CASE
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -9,6 +9,8 @@ One step from the same state, HIP path through the C ABI against the oracle:
     amplified by cond(I_c).  A cell of two uses the pseudo-inverse (cond 1).
   * FP32 and split forms: the oracle collides the GPU's post-stream state;
     e <= 2e-6.
+  * With the thermostat (MPC_MBS) the corrected relative velocities are
+    scaled to the drawn energy; the same bars apply.
   * Invariant at any size: per cell, momentum and angular momentum about the
     centre of mass are unchanged by the GPU's collision.
 """
@@ -46,7 +48,7 @@ def box_of(L, seed=1, density=10.0, g=(0.0, 0.0, 0.0), **kw):
 def oparams(box):
     return orc.Params(L=box["L"], h=box["h"], alpha=box["alpha"], kT=box["kT"],
                       mass=box["mass"], density=box["density"], seed=box["seed"],
-                      amc=True, g=box["g"])
+                      mbs=box["mbs"], amc=True, g=box["g"])
 
 
 def rel_err(vg, vo, box):
@@ -72,20 +74,23 @@ def cell_cond(key, off, perm, fr):
 
 
 AMC_CASES = [
-    # L, density, gravity, R, t0
-    ((16, 16, 16), 10.0, (0, 0, 0), 0, 0),
-    ((13, 9, 11), 10.0, (0, 0, 0), 1, 3),         # ragged tiles, sorted output
-    ((12, 10, 8), 10.0, (2e-3, 0, -1e-3), 3, 2),  # gravity, reorder step of R = 3
-    ((10, 10, 10), 2.0, (0, 0, 0), 0, 5),         # many cells of one, two, three
-    ((6, 5, 7), 60.0, (0, 0, 0), 1, 1),           # tiles in several passes
+    # L, density, gravity, R, t0, thermostat
+    ((16, 16, 16), 10.0, (0, 0, 0), 0, 0, False),
+    ((16, 16, 16), 10.0, (0, 0, 0), 0, 0, True),
+    ((13, 9, 11), 10.0, (0, 0, 0), 1, 3, False),         # ragged tiles, sorted output
+    ((13, 9, 11), 10.0, (0, 0, 0), 3, 2, True),          # reorder step of R = 3
+    ((12, 10, 8), 10.0, (2e-3, 0, -1e-3), 3, 2, True),   # gravity
+    ((10, 10, 10), 2.0, (0, 0, 0), 0, 5, False),         # many cells of one, two, three
+    ((10, 10, 10), 2.0, (0, 0, 0), 1, 6, True),
+    ((6, 5, 7), 60.0, (0, 0, 0), 1, 1, True),            # tiles in several passes
 ]
 
 
-@pytest.mark.parametrize("L,density,g,R,t0", AMC_CASES)
-def test_amc_fp64_one_step(mpc, L, density, g, R, t0):
-    box = box_of(L, seed=7 + t0, density=density, g=g)
-    x, v = synth.box_state(L, density=density, seed=13 + t0)
-    print(f"case amc fp64 L={L} density={density} R={R} t0={t0}", flush=True)
+@pytest.mark.parametrize("L,density,g,R,t0,mbs", AMC_CASES)
+def test_amc_fp64_one_step(mpc, L, density, g, R, t0, mbs):
+    box = box_of(L, seed=7 + t0, density=density, g=g, mbs=mbs)
+    x, v = synth.box_state(L, density=density, seed=13 + t0, kT=0.8 if mbs else 1.0)
+    print(f"case amc fp64 L={L} density={density} R={R} t0={t0} mbs={mbs}", flush=True)
     with mpc.Sim(box, form="fp64", reorder_every=R) as sim:
         if density > 30:
             sim.set_tiling(32, 0, 0)
@@ -112,13 +117,14 @@ def test_amc_fp64_one_step(mpc, L, density, g, R, t0):
     assert np.all(e <= tol)
 
 
-@pytest.mark.parametrize("form", ["fp32", "split"])
-def test_amc_reduced_precision_one_step(mpc, form):
+@pytest.mark.parametrize("form,mbs", [("fp32", False), ("split", False), ("fp32", True),
+                                      ("split", True)])
+def test_amc_reduced_precision_one_step(mpc, form, mbs):
     L = (16, 12, 10)
-    box = box_of(L, seed=9)
+    box = box_of(L, seed=9, mbs=mbs)
     x, v = synth.box_state(L, seed=21)
     t0 = 4
-    print(f"case amc form={form}", flush=True)
+    print(f"case amc form={form} mbs={mbs}", flush=True)
     with mpc.Sim(box, form=form) as sim:
         sim.set_state(x, v)
         _, v0 = sim.get_state()
@@ -171,9 +177,21 @@ def test_amc_conserves_angular_momentum_on_gpu(mpc, form):
     assert dP <= tol * 10 and dL <= tol * 10
 
 
-def test_amc_flag_combinations_refused(mpc):
-    for kw in ({"mbs": True}, {"walls": True}):
-        box = box_of((8, 8, 8), **kw)
-        with pytest.raises(mpc.MPCError) as e:
-            mpc.Sim(box)
-        assert e.value.code == mpc.EINVAL
+def test_amc_with_walls_refused(mpc):
+    box = box_of((8, 8, 8), walls=True)
+    with pytest.raises(mpc.MPCError) as e:
+        mpc.Sim(box)
+    assert e.value.code == mpc.EINVAL
+
+
+def test_amc_thermostat_relaxes_temperature(mpc):
+    """SRD+a heats the fluid on its own; with the thermostat the temperature
+    relaxes to kT from a hotter start."""
+    L = (16, 16, 16)
+    with mpc.Sim(box_of(L, seed=4, mbs=True), form="fp64") as sim:
+        x, v = synth.box_state(L, seed=44, kT=2.0)
+        sim.set_state(x, v)
+        sim.step(30)
+        T = sim.observables()["T"]
+    print(f"amc+mbs: T after 30 steps from kT = 2: {T:.4f}")
+    assert abs(T - 1.0) < 0.02

@@ -2,8 +2,8 @@
 (167,772,160 particles), thermostat on, FP64, reorder interval 20, in the
 launch configuration the benchmark uses, one step from a synthetic state.
 
-The same box with the collision SRD+a (Eqs. 3-4) instead of the
-thermostatted SRD is checked the same way.
+The same box with the angular-momentum-conserving collision SRD+a (Eqs. 3-4,
+thermostat on) is checked the same way.
 
 Post-stream positions, cell keys, the sort permutation and the offsets are
 compared with the oracle for every particle; velocities (e <= 1e-12) for the
@@ -34,11 +34,10 @@ def mpc():
 
 @pytest.mark.parametrize("t0,amc", [(19, False), (19, True)])
 def test_c2_full_size_one_step(mpc, t0, amc):
-    """amc: the same box with the collision SRD+a (Eqs. 3-4) in place of the
-    thermostatted SRD (the two are not combined)."""
+    """amc: the same box and thermostat with the collision SRD+a (Eqs. 3-4)."""
     box = synth.config("C2")
     if amc:
-        box = dict(box, mbs=False, amc=True)
+        box = dict(box, amc=True)
     L = box["L"]
     t_start = time.time()
     x, v = synth.box_state(L, seed=2024)
