@@ -342,6 +342,8 @@ def main():
                     "collide_roofline_frac": n2 * 2 * STATE_BYTES[fm] / (c2 * 1e-3) / 1e9
                     / HBM_PEAK_GBS,
                     "launch": run_box.last_tiling, "T_end": o2["T"]}
+                tra = traffic_record("amc_" + fm, "C2", R)
+                forms[form]["collide_traffic_bytes"] = tra["bytes_per_launch"] if tra else None
                 print(f"[{form} C2] {w2 * 1e3 / args.steps:.3f} ms/step collide {c2:.3f} ms",
                       file=sys.stderr)
             elif form == "c3":

@@ -23,7 +23,8 @@
  *     (t + 1) mod R = 0 (R = 0: never).
  * The arguments follow the paper's statement of the method: box in cells,
  * cell size a, mean density <N_c>, time step h, rotation angle alpha, k_B T,
- * mass m, and a main random seed (Sec. III.D.4, "passed as a parameter").
+ * mass m, and a main random seed (Sec. III.E: the main seed may be given as
+ * a parameter).
  *
  * Conventions for every call:
  *   - All calls are extern "C"; no C++ exception crosses this boundary.

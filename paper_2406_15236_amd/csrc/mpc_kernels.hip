@@ -1121,7 +1121,8 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
   }
   // SRD+a (Eqs. 3-4, periodic boxes): omega = I^-1 dL with
   // dL = sum r_ic x (u_i - D u_i) and I the inertia tensor, both about the
-  // centre of mass of the cell-frame positions (the mass m cancels).  A pair
+  // centre of mass of the cell-frame positions (the mass m cancels; the
+  // thermostat's energy below restores it).  A pair
   // uses the pseudo-inverse of its singular I (omega = dL / (tr I / 2), since
   // tr I = |r_1 - r_2|^2), three or more Cramer's rule, and det I = 0 gives
   // omega = 0.  Both lanes of the pair build identical totals.
@@ -1137,46 +1138,62 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
       const double o = pair_xor(rc[k]);
       rc[k] = (half ? o + rc[k] : rc[k] + o) / (double)(nf ? nf : 1u);
     }
-    // dL[0..2]; I: xx, yy, zz, xy, xz, yz; with the thermostat also the
-    // angular momentum L0 = sum r_ic x u_i
-    constexpr int NA = M ? 12 : 9;
-    double a9[NA];
+    // Moments about the centre of mass: M = sum r_ic u_i^T and S = sum r_ic
+    // r_ic^T (15 sums, no per-particle rotation).  Then I = tr(S) 1 - S, the
+    // angular momentum before the rotation L0 = eps : M, after it
+    // L_D = sum r_ic x D u_i = eps : (M D^T), and dL = L0 - L_D.
+    double mm[9], ss[6];  // mm[3a+b] = M_ab; ss: xx, yy, zz, xy, xz, yz
 #pragma unroll
-    for (int k = 0; k < NA; ++k) a9[k] = 0.0;
-    const double n[3] = {cd.n[0], cd.n[1], cd.n[2]};
+    for (int k = 0; k < 9; ++k) mm[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ss[k] = 0.0;
     for (uint32_t q = qb; q < qe; ++q) {
       const double r[3] = {frame_pos(sx0[q], s[0]) - rc[0], frame_pos(sx1[q], s[1]) - rc[1],
                            frame_pos(sx2[q], s[2]) - rc[2]};
       const double u[3] = {(double)sv0[q] - V[0], (double)sv1[q] - V[1], (double)sv2[q] - V[2]};
-      double du[3];
-      rotate<double>(B.ca, B.sa, B.omc, n, u, du);
-      const double w[3] = {u[0] - du[0], u[1] - du[1], u[2] - du[2]};
-      a9[0] = a9[0] + (r[1] * w[2] - r[2] * w[1]);
-      a9[1] = a9[1] + (r[2] * w[0] - r[0] * w[2]);
-      a9[2] = a9[2] + (r[0] * w[1] - r[1] * w[0]);
-      a9[3] = a9[3] + (r[1] * r[1] + r[2] * r[2]);
-      a9[4] = a9[4] + (r[0] * r[0] + r[2] * r[2]);
-      a9[5] = a9[5] + (r[0] * r[0] + r[1] * r[1]);
-      a9[6] = a9[6] - r[0] * r[1];
-      a9[7] = a9[7] - r[0] * r[2];
-      a9[8] = a9[8] - r[1] * r[2];
-      if constexpr (M) {
-        a9[9] = a9[9] + (r[1] * u[2] - r[2] * u[1]);
-        a9[10] = a9[10] + (r[2] * u[0] - r[0] * u[2]);
-        a9[11] = a9[11] + (r[0] * u[1] - r[1] * u[0]);
-      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b2 = 0; b2 < 3; ++b2) mm[3 * a + b2] = fma(r[a], u[b2], mm[3 * a + b2]);
+      ss[0] = fma(r[0], r[0], ss[0]);
+      ss[1] = fma(r[1], r[1], ss[1]);
+      ss[2] = fma(r[2], r[2], ss[2]);
+      ss[3] = fma(r[0], r[1], ss[3]);
+      ss[4] = fma(r[0], r[2], ss[4]);
+      ss[5] = fma(r[1], r[2], ss[5]);
     }
 #pragma unroll
-    for (int k = 0; k < NA; ++k) {
-      const double o = pair_xor(a9[k]);
-      a9[k] = half ? o + a9[k] : a9[k] + o;
+    for (int k = 0; k < 9; ++k) {
+      const double o = pair_xor(mm[k]);
+      mm[k] = half ? o + mm[k] : mm[k] + o;
     }
-    const double xx = a9[3], yy = a9[4], zz = a9[5], xy = a9[6], xz = a9[7], yz = a9[8];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const double o = pair_xor(ss[k]);
+      ss[k] = half ? o + ss[k] : ss[k] + o;
+    }
+    const double xx = ss[1] + ss[2], yy = ss[0] + ss[2], zz = ss[0] + ss[1];
+    const double xy = -ss[3], xz = -ss[4], yz = -ss[5];
+    // rotation matrix D(alpha, n), row major
+    const double n[3] = {cd.n[0], cd.n[1], cd.n[2]};
+    const double ca = B.ca, sa = B.sa, omc = B.omc;
+    const double D[9] = {ca + omc * n[0] * n[0],        omc * n[0] * n[1] - sa * n[2],
+                         omc * n[0] * n[2] + sa * n[1], omc * n[1] * n[0] + sa * n[2],
+                         ca + omc * n[1] * n[1],        omc * n[1] * n[2] - sa * n[0],
+                         omc * n[2] * n[0] - sa * n[1], omc * n[2] * n[1] + sa * n[0],
+                         ca + omc * n[2] * n[2]};
+    // (M D^T)_bc = row b of M . row c of D
+    auto md = [&](int b2, int c) {
+      return mm[3 * b2] * D[3 * c] + mm[3 * b2 + 1] * D[3 * c + 1] + mm[3 * b2 + 2] * D[3 * c + 2];
+    };
+    const double LD[3] = {md(1, 2) - md(2, 1), md(2, 0) - md(0, 2), md(0, 1) - md(1, 0)};
+    double a9[3] = {(mm[5] - mm[7]) - LD[0], (mm[6] - mm[2]) - LD[1], (mm[1] - mm[3]) - LD[2]};
     if (nf == 2) {
       const double hm = 0.5 * (xx + yy + zz);
       if (hm > 0.0) {
+        const double ih = 1.0 / hm;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) om[k] = a9[k] / hm;
+        for (int k = 0; k < 3; ++k) om[k] = a9[k] * ih;
       }
     } else if (nf >= 3) {
       // adjugate of the symmetric I
@@ -1184,15 +1201,16 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
       const double c11 = xx * zz - xz * xz, c12 = xy * xz - xx * yz, c22 = xx * yy - xy * xy;
       const double det = xx * c00 + xy * c01 + xz * c02;
       if (det != 0.0) {
-        om[0] = (c00 * a9[0] + c01 * a9[1] + c02 * a9[2]) / det;
-        om[1] = (c01 * a9[0] + c11 * a9[1] + c12 * a9[2]) / det;
-        om[2] = (c02 * a9[0] + c12 * a9[1] + c22 * a9[2]) / det;
+        const double id = 1.0 / det;
+        om[0] = (c00 * a9[0] + c01 * a9[1] + c02 * a9[2]) * id;
+        om[1] = (c01 * a9[0] + c11 * a9[1] + c12 * a9[2]) * id;
+        om[2] = (c02 * a9[0] + c12 * a9[1] + c22 * a9[2]) * id;
       }
     }
     if constexpr (M) {
       // the thermostat scales the corrected relative velocities D u_i +
       // omega x r_ic to the drawn energy; their kinetic energy is
-      // K + m (2 omega . (L0 - dL) + omega . I omega), K that of the u_i
+      // K + m (2 omega . L_D + omega . I omega), K that of the u_i
       kappa = 1.0;
       if (cd.Ek > 0.0) {
         const double Io[3] = {xx * om[0] + xy * om[1] + xz * om[2],
@@ -1201,7 +1219,7 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
         double cr = 0.0, q = 0.0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          cr = cr + om[k] * (a9[9 + k] - a9[k]);
+          cr = cr + om[k] * LD[k];
           q = q + om[k] * Io[k];
         }
         const double K2 = K + m * (2.0 * cr + q);
