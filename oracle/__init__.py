@@ -38,7 +38,7 @@ def build(out: str = LIB_PATH, src: str = _SRC) -> str:
 
 class _Params(C.Structure):
     _fields_ = [("L", C.c_int32 * 3), ("walls", C.c_int32), ("mbs", C.c_int32),
-                ("amc", C.c_int32), ("h", C.c_double), ("alpha", C.c_double),
+                ("amc", C.c_int32), ("fixed", C.c_int32), ("h", C.c_double), ("alpha", C.c_double),
                 ("kT", C.c_double), ("mass", C.c_double), ("density", C.c_double),
                 ("g", C.c_double * 3), ("seed", C.c_uint64)]
 
@@ -56,12 +56,14 @@ class Params:
     mbs: bool = False
     walls: bool = False
     amc: bool = False
+    fixed: bool = False
     g: tuple = field(default_factory=lambda: (0.0, 0.0, 0.0))
 
     def c(self) -> _Params:
         p = _Params()
         p.L[:] = [int(v) for v in self.L]
         p.walls, p.mbs, p.amc = int(self.walls), int(self.mbs), int(self.amc)
+        p.fixed = int(self.fixed)
         p.h, p.alpha, p.kT, p.mass = self.h, self.alpha, self.kT, self.mass
         p.density = self.density
         p.g[:] = [float(v) for v in self.g]
@@ -253,6 +255,8 @@ def collide(p: Params, t: int, v, perm, offset, cells: bool = False, x=None):
         xp = _f64(x)
     rc = lib().orc_collide(C.byref(p.c()), t, v.shape[1], xp, _f64(v), _u32(perm),
                            _u32(offset), ncell, _f64(co) if cells else None)
+    if rc == -3:
+        raise ValueError("a fixed-point summand is outside |x| < 2^37")
     if rc != 0:
         raise ValueError("SRD+a needs positions and is defined for periodic boxes")
     if cells:
@@ -279,6 +283,8 @@ def step(p: Params, t: int, x, v, reorder: bool = False, binning: bool = False):
                         _u32(key), _u32(perm), _u32(offset))
     if rc == -2:
         raise ValueError("SRD+a is defined for periodic boxes")
+    if rc == -3:
+        raise ValueError("a fixed-point summand is outside |x| < 2^37")
     if rc != 0:
         raise ValueError("position outside the box or not finite")
     if binning:

@@ -351,6 +351,39 @@ void orc_rotate(double alpha, const double n[3], const double u[3], double out[3
 /* Cells with fewer than two particles are left unchanged.  Afterwards the    */
 /* gravity kick v <- v + g h is applied to every particle (reading: gravity). */
 /* ------------------------------------------------------------------------ */
+/* One cell sum (Sec. III.C, reproducibility).  Without p->fixed: FP64
+ * additions in the order the terms come.  With p->fixed: each term x is the
+ * integer trunc(x 2^80) (a 128-bit integer with 80 fractional bits), the sum
+ * is the exact integer sum, and its value is that integer rounded once to the
+ * nearest double, times 2^-80; it does not depend on the order of the terms.
+ * Terms need |x| < 2^37, so that no sum of at most 2^10 terms can overflow;
+ * a larger term sets *bad. */
+typedef struct {
+  int fixed;
+  double d;
+  __int128 s;
+} orc_sum;
+
+static orc_sum sum_new(const orc_params* p) {
+  orc_sum a;
+  a.fixed = p->fixed;
+  a.d = 0.0;
+  a.s = 0;
+  return a;
+}
+
+static void sum_add(orc_sum* a, double x, int* bad) {
+  if (!a->fixed) {
+    a->d = a->d + x;
+  } else if (fabs(x) < 0x1p37) {
+    a->s += (__int128)(x * 0x1p80);
+  } else {
+    *bad = 1;
+  }
+}
+
+static double sum_val(const orc_sum* a) { return a->fixed ? (double)a->s * 0x1p-80 : a->d; }
+
 /* Sec. II Eqs.(3)-(4), SRD+a: after the rotation, each particle also gets
  * omega x r_ic, with r_ic its position relative to the cell's centre of mass
  * and omega = m I^-1 sum_i r_ic x (u_i - D u_i) (u_i = v_i - v_cm, D the
@@ -365,20 +398,23 @@ void orc_rotate(double alpha, const double n[3], const double u[3], double out[3
  * scaling is applied to the corrected relative velocities (see orc_collide). */
 static void amc_cell(const orc_params* p, const double s[3], int64_t n, const double* x,
                      const double* v0, double* v, const uint32_t* perm, uint32_t b, uint32_t e,
-                     const double V[3], const double ax[3], double ca, double sa, double omc) {
+                     const double V[3], const double ax[3], double ca, double sa, double omc,
+                     int* bad) {
   const double m = p->mass;
   const int64_t nf = (int64_t)e - (int64_t)b;
-  double rc[3] = {0.0, 0.0, 0.0};
+  orc_sum rs[3] = {sum_new(p), sum_new(p), sum_new(p)};
   for (uint32_t j = b; j < e; ++j) {
     uint32_t i = perm[j];
     for (int k = 0; k < 3; ++k) {
       double y = x[k * n + i] + s[k];
-      rc[k] = rc[k] + (y - floor(y));
+      sum_add(&rs[k], y - floor(y), bad);
     }
   }
-  for (int k = 0; k < 3; ++k) rc[k] = rc[k] / (double)nf;
-  double dL[3] = {0.0, 0.0, 0.0};
-  double I[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double rc[3];
+  for (int k = 0; k < 3; ++k) rc[k] = sum_val(&rs[k]) / (double)nf;
+  orc_sum dLs[3], Is[9];
+  for (int k = 0; k < 3; ++k) dLs[k] = sum_new(p);
+  for (int k = 0; k < 9; ++k) Is[k] = sum_new(p);
   for (uint32_t j = b; j < e; ++j) {
     uint32_t i = perm[j];
     double r[3], u[3], d[3], w[3];
@@ -389,13 +425,16 @@ static void amc_cell(const orc_params* p, const double s[3], int64_t n, const do
     }
     rotate_cs(ca, sa, omc, ax, u, d);
     for (int k = 0; k < 3; ++k) w[k] = u[k] - d[k];
-    dL[0] = dL[0] + m * (r[1] * w[2] - r[2] * w[1]);
-    dL[1] = dL[1] + m * (r[2] * w[0] - r[0] * w[2]);
-    dL[2] = dL[2] + m * (r[0] * w[1] - r[1] * w[0]);
+    sum_add(&dLs[0], m * (r[1] * w[2] - r[2] * w[1]), bad);
+    sum_add(&dLs[1], m * (r[2] * w[0] - r[0] * w[2]), bad);
+    sum_add(&dLs[2], m * (r[0] * w[1] - r[1] * w[0]), bad);
     double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
     for (int a = 0; a < 3; ++a)
-      for (int c = 0; c < 3; ++c) I[3 * a + c] = I[3 * a + c] + m * ((a == c ? r2 : 0.0) - r[a] * r[c]);
+      for (int c = 0; c < 3; ++c) sum_add(&Is[3 * a + c], m * ((a == c ? r2 : 0.0) - r[a] * r[c]), bad);
   }
+  double dL[3], I[9];
+  for (int k = 0; k < 3; ++k) dL[k] = sum_val(&dLs[k]);
+  for (int k = 0; k < 9; ++k) I[k] = sum_val(&Is[k]);
   double om[3] = {0.0, 0.0, 0.0};
   if (nf == 2) {
     uint32_t i1 = perm[b], i2 = perm[b + 1];
@@ -437,6 +476,7 @@ static void amc_cell(const orc_params* p, const double s[3], int64_t n, const do
 int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, double* v,
                 const uint32_t* perm, const uint32_t* offset, int64_t ncell, double* cell_out) {
   if (p->amc && (p->walls || !x)) return -2;
+  int bad = 0; /* a fixed-point summand out of range */
   const double m = p->mass;
   double* v0 = NULL; /* pre-collision velocities (SRD+a) */
   if (p->amc) {
@@ -464,22 +504,25 @@ int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, dou
     }
     int64_t ntot = nf + np;
 
-    double P[3] = {0.0, 0.0, 0.0};
+    orc_sum Ps[3] = {sum_new(p), sum_new(p), sum_new(p)};
     for (uint32_t j = b; j < e; ++j) {
       uint32_t i = perm[j];
-      for (int k = 0; k < 3; ++k) P[k] = P[k] + m * v[k * n + i];
+      for (int k = 0; k < 3; ++k) sum_add(&Ps[k], m * v[k * n + i], &bad);
     }
+    /* phantoms follow in their draw order */
+    double P[3] = {sum_val(&Ps[0]), sum_val(&Ps[1]), sum_val(&Ps[2])};
     for (int32_t q = 0; q < np; ++q)
       for (int k = 0; k < 3; ++k) P[k] = P[k] + m * vp[3 * q + k];
     double M = (double)ntot * m;
     double V[3] = {P[0] / M, P[1] / M, P[2] / M};
 
-    double K = 0.0;
+    orc_sum Ks = sum_new(p);
     for (uint32_t j = b; j < e; ++j) {
       uint32_t i = perm[j];
       double dx = v[i] - V[0], dy = v[n + i] - V[1], dz = v[2 * n + i] - V[2];
-      K = K + m * (dx * dx + dy * dy + dz * dz);
+      sum_add(&Ks, m * (dx * dx + dy * dy + dz * dz), &bad);
     }
+    double K = sum_val(&Ks);
     for (int32_t q = 0; q < np; ++q) {
       double dx = vp[3 * q] - V[0], dy = vp[3 * q + 1] - V[1], dz = vp[3 * q + 2] - V[2];
       K = K + m * (dx * dx + dy * dy + dz * dz);
@@ -531,17 +574,16 @@ int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, dou
       }
     }
     if (p->amc) {
-      amc_cell(p, s, n, x, v0, v, perm, b, e, V, ax, ca, sa, omc);
+      amc_cell(p, s, n, x, v0, v, perm, b, e, V, ax, ca, sa, omc, &bad);
       /* MBS with SRD+a: kappa sets the cell's relative kinetic energy after
        * the corrected collision to the drawn E_k */
-      double K2 = 0.0;
+      orc_sum K2s = sum_new(p);
       for (uint32_t j = b; j < e; ++j) {
         uint32_t i = perm[j];
-        for (int k = 0; k < 3; ++k) {
-          double du = v[k * n + i] - V[k];
-          K2 = K2 + m * du * du;
-        }
+        double du[3] = {v[i] - V[0], v[n + i] - V[1], v[2 * n + i] - V[2]};
+        sum_add(&K2s, m * (du[0] * du[0] + du[1] * du[1] + du[2] * du[2]), &bad);
       }
+      double K2 = sum_val(&K2s);
       kappa = 1.0;
       if (have_ek && K2 > 0.0) kappa = sqrt((2.0 * Ek) / K2);
       Kpost = 0.0;
@@ -570,7 +612,7 @@ int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, dou
       for (int64_t i = 0; i < n; ++i) v[k * n + i] = v[k * n + i] + gh;
     }
   }
-  return 0;
+  return bad ? -3 : 0;
 }
 
 /* Sec. III.B.3: particles stored in cell order (here: this step's order). */

@@ -15,6 +15,7 @@
  *   Sec. II (Boundary conditions) bounce-back, phantom particles
  *   Sec. II (External fields) constant gravity
  *   Sec. III.B.3 (Permanent exchange) reorder by cell -> orc_reorder
+ *   Sec. III.C      fixed-point cell sums (optional)  -> orc_collide
  * Where the paper is silent the reading used is listed in the design doc under
  * "Readings of the paper"; each function below names the reading it takes.
  *
@@ -37,6 +38,8 @@ typedef struct {
   int32_t  amc;       /* 1: cell angular momentum conserved (SRD+a, Eqs. 3-4);
                          periodic boxes only; with mbs the scaling follows the
                          correction                                            */
+  int32_t  fixed;     /* 1: cell sums of fluid terms in fixed point (Sec.
+                         III.C, reproducibility): independent of the order  */
   double   h;         /* MPC time step                                         */
   double   alpha;     /* rotation angle, radians                               */
   double   kT;        /* k_B T                                                 */
@@ -105,7 +108,8 @@ void orc_rotate(double alpha, const double n[3], const double u[3], double out[3
 /* Collision of step t on already streamed velocities v, given the sort.
  * x (post-stream positions) is read only with p->amc (it may be NULL
  * otherwise); cell_out (optional) receives ORC_CELL_STRIDE doubles per cell.
- * Returns -2 for amc with walls or without x. */
+ * Returns -2 for amc with walls or without x, -3 (p->fixed) for a summand
+ * outside the fixed-point range |x| < 2^37. */
 int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, double* v,
                 const uint32_t* perm, const uint32_t* offset, int64_t ncell,
                 double* cell_out);

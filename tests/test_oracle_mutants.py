@@ -49,13 +49,16 @@ MUTANTS = {
     "energy_half": ("nadd(&E, 0.5 * m * e);", "nadd(&E, m * e);"),
     "amc_omega_sign": ("om[k] = dk / det;", "om[k] = -dk / det;"),
     "amc_inertia_no_r2": ("(a == c ? r2 : 0.0) - r[a] * r[c]", "0.0 - r[a] * r[c]"),
-    "amc_about_corner": ("for (int k = 0; k < 3; ++k) rc[k] = rc[k] / (double)nf;",
+    "amc_about_corner": ("for (int k = 0; k < 3; ++k) rc[k] = sum_val(&rs[k]) / (double)nf;",
                          "for (int k = 0; k < 3; ++k) rc[k] = 0.0;"),
     "amc_pair_factor": ("om[k] = dL[k] / (m * d2 / 2.0);", "om[k] = dL[k] / (m * d2);"),
     "amc_torque_post": ("u[k] = v0[k * n + i] - V[k];", "u[k] = v[k * n + i] - V[k];"),
     "amc_mbs_pre_energy": ("if (have_ek && K2 > 0.0) kappa = sqrt((2.0 * Ek) / K2);",
                            "if (have_ek && K2 > 0.0) kappa = sqrt((2.0 * Ek) / K);"),
     "amc_mbs_scaled_twice": ("const double kr = p->amc ? 1.0 : kappa;", "const double kr = kappa;"),
+    "fixed_rounds_terms": ("a->s += (__int128)(x * 0x1p80);", "a->s += (__int128)nearbyint(x * 0x1p80);"),
+    "fixed_scale_back": ("(double)a->s * 0x1p-80", "(double)a->s * 0x1p-79"),
+    "fixed_range": ("} else if (fabs(x) < 0x1p37) {", "} else if (fabs(x) < 0x1p60) {"),
 }
 
 FAST_PINS = [
@@ -69,13 +72,16 @@ FAST_PINS = [
     "test_observables_against_fsum", "test_reorder_is_gather", "test_philox_matches_rocrand",
     "test_amc_conserves_angular_momentum", "test_amc_correction_is_rigid_rotation",
     "test_amc_alpha_zero_is_identity", "test_amc_refused_with_walls", "test_amc_with_thermostat",
+    "test_fixed_sums_exact", "test_fixed_sums_order_independent", "test_fixed_sums_range",
 ]
 
 PARAMS = {"test_keys_exact_floor": [{"walls": False}, {"walls": True}],
           "test_collision_is_rotation_of_relative_velocity": [{"mbs": False}, {"mbs": True}],
           "test_gamma_sampler_distribution": [{"shape": 3.0}, {"shape": 13.5}],
           "test_amc_conserves_angular_momentum": [{"L": (6, 6, 6), "density": 10.0},
-                                                  {"L": (8, 8, 8), "density": 1.5}]}
+                                                  {"L": (8, 8, 8), "density": 1.5}],
+          "test_fixed_sums_order_independent": [{"amc": False}, {"amc": True}],
+          "test_fixed_sums_exact": [{"vscale": 1.0}, {"vscale": 1e-13}]}
 
 
 @pytest.fixture(scope="module")

@@ -673,3 +673,83 @@ def test_amc_with_thermostat(orc):
     np.testing.assert_allclose(cells[sel, 15], 2 * cells[sel, 10], rtol=1e-12)
     u = stats.gamma.cdf(cells[sel, 10] / pm.kT, 1.5 * (cells[sel, 0] - 1))
     assert stats.kstest(u, "uniform").pvalue > 1e-3
+
+
+# --- fixed-point cell sums (Sec. III.C) ---------------------------------------
+def _fixed_state(L, seed):
+    """Maxwellian velocities with a few tiny ones, so that some terms are not
+    multiples of 2^-80 and the truncation rule matters."""
+    x, v = synth.box_state(L, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    tiny = rng.random(x.shape[1]) < 0.05
+    v[:, tiny] = rng.normal(size=(3, tiny.sum())) * 1e-13
+    return x, v
+
+
+def _exact_fixed_sum(terms):
+    """The definition with Python integers: sum of trunc(t 2^80), rounded once
+    (int / int is correctly rounded) and scaled by 2^-80."""
+    return sum(int(t * 2 ** 80) for t in terms) / 2 ** 80
+
+
+@pytest.mark.parametrize("vscale", [1.0, 1e-13])
+def test_fixed_sums_exact(orc, vscale):
+    """Sec. III.C: with fixed-point sums, each cell's momentum, mean velocity
+    and kinetic energy equal the exact integer definition bit for bit.  With
+    tiny velocities the sums are far below 1, so that the truncation of each
+    term to the 2^-80 grid shows in the rounded result."""
+    L = (6, 6, 6)
+    p = orc.Params(L=L, mbs=True, fixed=True, mass=1.3, seed=41)
+    x, v = _fixed_state(L, 43)
+    v *= vscale
+    xs, vs, key, perm, off, v2, cells = _one_step_parts(orc, p, 3, x, v)
+    checked = 0
+    for c in range(p.ncells):
+        idx = perm[off[c]:off[c + 1]]
+        if idx.size == 0:
+            continue
+        m = p.mass
+        P = [_exact_fixed_sum(float(m * vv) for vv in vs[k, idx]) for k in range(3)]
+        assert [cells[c, 12 + k] for k in range(3)] == P
+        V = [Pk / (idx.size * m) for Pk in P]
+        assert [cells[c, 2 + k] for k in range(3)] == V
+        terms = []
+        for i in idx:
+            dx, dy, dz = (float(vs[k, i]) - V[k] for k in range(3))
+            terms.append(m * (dx * dx + dy * dy + dz * dz))
+        assert cells[c, 5] == _exact_fixed_sum(terms)
+        checked += 1
+    assert checked > 0.9 * p.ncells
+
+
+@pytest.mark.parametrize("amc", [False, True])
+def test_fixed_sums_order_independent(orc, amc):
+    """Sec. III.C: with fixed-point sums the trajectory does not depend on the
+    order in which particles are stored; with FP64 sums it does (at rounding
+    level)."""
+    L = (5, 6, 7)
+    x, v = _fixed_state(L, 47)
+    perm = np.random.default_rng(5).permutation(x.shape[1])
+    inv = np.argsort(perm)
+    runs = {}
+    for fixed in (False, True):
+        p = orc.Params(L=L, mbs=True, amc=amc, fixed=fixed, seed=53)
+        xa, va = orc.run(p, x, v, 3)
+        xb, vb = orc.run(p, x[:, perm], v[:, perm], 3)
+        runs[fixed] = (np.array_equal(xa, xb[:, inv]), np.array_equal(va, vb[:, inv]))
+    assert runs[True] == (True, True)
+    assert runs[False][1] is False
+
+
+def test_fixed_sums_range(orc):
+    """A summand outside |x| < 2^37 is refused in fixed-point mode."""
+    L = (4, 4, 4)
+    x, v = synth.box_state(L, seed=3)
+    v[0, 7] = 2.0 ** 19  # its kinetic-energy term is about 2^38
+    refused = False
+    try:
+        orc.step(orc.Params(L=L, fixed=True), 0, x, v)
+    except ValueError:
+        refused = True
+    assert refused
+    orc.step(orc.Params(L=L), 0, x, v)
