@@ -64,7 +64,7 @@ enum {
   MPC_WALLS_Z = 2u, /* no-slip walls at z = 0 and z = L[2] = H: bounce-back streaming
                        and phantom particles in wall-cut cells (Sec. II, Boundary
                        conditions); x and y stay periodic                              */
-  MPC_AMC = 4u      /* angular-momentum-conserving collision SRD+a (Sec. II, Eqs. 3-4):
+  MPC_AMC = 4u,     /* angular-momentum-conserving collision SRD+a (Sec. II, Eqs. 3-4):
                        v_i' = v_cm + D u_i + omega x r_ic with omega = I^-1 dL, where
                        r_ic is the position relative to the cell's centre of mass in
                        the shifted cell's frame, frac(x/a + s), I the inertia tensor
@@ -75,6 +75,15 @@ enum {
                        D u_i + omega x r_ic so that their kinetic energy equals the
                        drawn E_k (angular momentum is then scaled by kappa).
                        Periodic boxes only: with MPC_WALLS_Z -> MPC_EINVAL           */
+  MPC_FIXED_SUMS = 8u /* reproducible cell sums (Sec. III.C): every sum over a cell's
+                       fluid particles (momentum, kinetic energy, the SRD+a moments)
+                       is exact in fixed point -- each FP64 term x becomes the
+                       integer trunc(x 2^80) in 128 bits, the sum is rounded once
+                       to FP64 -- so the trajectory does not depend on the order in
+                       which particles are stored (caller's order, reorder interval,
+                       tiling).  Terms must satisfy |x| < 2^37 in cell units (speeds
+                       below 2^18.5 cells per unit time); otherwise the next
+                       synchronising call returns MPC_ERANGE                        */
 };
 
 /* Error codes. */
@@ -82,8 +91,9 @@ enum {
   MPC_OK = 0,
   MPC_EINVAL = -1,   /* invalid argument (box, a, h, alpha, density, kT, m, form, flags) */
   MPC_ENOSPACE = -2, /* workspace smaller than mpc_workspace_bytes                       */
-  MPC_ERANGE = -3,   /* N or cell count >= 2^31, box too large for the form, or a cell
-                        that held more than MPC_MAX_CELL_PARTICLES particles             */
+  MPC_ERANGE = -3,   /* N or cell count >= 2^31, box too large for the form, a cell
+                        that held more than MPC_MAX_CELL_PARTICLES particles, or (with
+                        MPC_FIXED_SUMS) a summand outside the fixed-point range       */
   MPC_EHIP = -4,     /* HIP runtime error (message kept in the handle)                  */
   MPC_ESTATE = -5    /* a particle left the box or became non-finite                    */
 };
@@ -97,7 +107,8 @@ enum {
 typedef struct {
   int32_t  L[3];          /* box in cells; with MPC_WALLS_Z, L[2] = H                     */
   int32_t  form;          /* mpc_form (same for all boxes)                                 */
-  uint32_t flags;         /* MPC_MBS | MPC_WALLS_Z | MPC_AMC (same for all boxes)         */
+  uint32_t flags;         /* MPC_MBS | MPC_WALLS_Z | MPC_AMC | MPC_FIXED_SUMS (same for
+                             all boxes)                                                   */
   int32_t  reorder_every; /* R: renumber particles in (cell, index) order after every
                              R-th step; 0 = never (same for all boxes)                    */
   double   a;             /* cell size, > 0                                                */

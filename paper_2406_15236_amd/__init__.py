@@ -19,7 +19,7 @@ import numpy as np
 from .build import LIB
 
 FP64, FP32, SPLIT32 = 0, 1, 2
-MBS, WALLS_Z, AMC = 1, 2, 4
+MBS, WALLS_Z, AMC, FIXED_SUMS = 1, 2, 4, 8
 FORMS = {"fp64": FP64, "fp32": FP32, "split": SPLIT32}
 MAX_CELL_PARTICLES = 1024
 
@@ -123,7 +123,7 @@ def make_params(box: dict, form="fp64", flags: int | None = None, reorder_every:
     p.form = FORMS[form] if isinstance(form, str) else int(form)
     if flags is None:
         flags = ((MBS if box.get("mbs") else 0) | (WALLS_Z if box.get("walls") else 0)
-                 | (AMC if box.get("amc") else 0))
+                 | (AMC if box.get("amc") else 0) | (FIXED_SUMS if box.get("fixed") else 0))
     p.flags = int(flags)
     p.reorder_every = int(reorder_every)
     p.a = float(box.get("a", a))

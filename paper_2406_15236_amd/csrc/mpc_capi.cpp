@@ -58,7 +58,8 @@ int validate(const mpc_params* p, int32_t nbox, std::string* why) {
       return MPC_EINVAL;
     };
     if (q.form < MPC_FP64 || q.form > MPC_SPLIT32) return bad("unknown form");
-    if (q.flags & ~(uint32_t)(MPC_MBS | MPC_WALLS_Z | MPC_AMC)) return bad("unknown flags");
+    if (q.flags & ~(uint32_t)(MPC_MBS | MPC_WALLS_Z | MPC_AMC | MPC_FIXED_SUMS))
+      return bad("unknown flags");
     if ((q.flags & MPC_AMC) && (q.flags & MPC_WALLS_Z))
       return bad("MPC_AMC is defined for periodic boxes (no MPC_WALLS_Z)");
     if (q.form != p[0].form || q.flags != p[0].flags || q.reorder_every != p[0].reorder_every)
@@ -295,6 +296,10 @@ int check_sticky(mpc_sim* s) {
     s->err = "a cell held more than MPC_MAX_CELL_PARTICLES particles";
     return MPC_ERANGE;
   }
+  if (c.err & kErrFixRange) {
+    s->err = "a fixed-point summand was outside |x| < 2^37 (cell units)";
+    return MPC_ERANGE;
+  }
   return MPC_OK;
 }
 
@@ -521,6 +526,7 @@ int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
   s->L.walls = (p[0].flags & MPC_WALLS_Z) ? 1 : 0;
   s->L.mbs = (p[0].flags & MPC_MBS) ? 1 : 0;
   s->L.amc = (p[0].flags & MPC_AMC) ? 1 : 0;
+  s->L.fixed = (p[0].flags & MPC_FIXED_SUMS) ? 1 : 0;
   s->L.nbox = (uint32_t)nbox;
   s->L.ntot = P.ntot;
   s->L.ctot = P.ctot;
@@ -534,7 +540,7 @@ int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
     s->num_cu = prop.multiProcessorCount;
   s->occupancy = 2;
-  if (collide_occupancy(s->form, s->L.walls, s->L.mbs, s->L.amc, &s->occupancy) != hipSuccess ||
+  if (collide_occupancy(s->L, &s->occupancy) != hipSuccess ||
       s->occupancy < 1)
     s->occupancy = 1;
   build_tiles(s);

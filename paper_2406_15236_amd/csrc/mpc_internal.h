@@ -19,7 +19,7 @@ enum : uint32_t { kTagShift = 1, kTagAxis = 2, kTagThermo = 3, kTagPhantom = 4,
                   kTagInitPos = 5, kTagInitVel = 6 };
 
 // Sticky error bits in Ctrl::err.
-enum : uint32_t { kErrKey = 1u, kErrCellOverflow = 2u };
+enum : uint32_t { kErrKey = 1u, kErrCellOverflow = 2u, kErrFixRange = 4u };
 
 enum : int { kFormF64 = 0, kFormF32 = 1, kFormSplit = 2 };
 
@@ -114,6 +114,7 @@ struct Launch {
   int form;
   int round_phantoms;      // split form: phantom velocities rounded to FP32
   int walls, mbs, amc;     // feature flags (identical for all boxes)
+  int fixed;               // fixed-point cell sums
   uint32_t nbox;
   uint64_t ntot, ctot;     // particles, cells over all boxes
   uint32_t ntiles, npblocks, nscan;
@@ -138,6 +139,6 @@ hipError_t launch_obs_pass1(const Dev& d, const Launch& l);
 hipError_t launch_obs_pass2(const Dev& d, const Launch& l, const double* vmean_dev);
 hipError_t launch_remove_mean(const Dev& d, const Launch& l, const double* vmean_dev);
 hipError_t launch_canon_perm(const Dev& d, const Launch& l, const uint32_t* ids);
-hipError_t collide_occupancy(int form, int walls, int mbs, int amc, int* blocks_per_cu);
+hipError_t collide_occupancy(const Launch& l, int* blocks_per_cu);  // flags of l only
 
 }  // namespace mpc

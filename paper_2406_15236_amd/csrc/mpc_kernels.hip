@@ -959,8 +959,8 @@ struct CellLdsAmc : CellLds {
   double om[3];
 };
 struct CellLdsSplitAmc : CellLdsSplit {
-  float rc[3];
-  float om[3];
+  double rc[3];  // FP64: the correction is formed in FP64 and rounded once
+  double om[3];
 };
 template <int F, bool A>
 struct CellRec {
@@ -1013,7 +1013,76 @@ __device__ __forceinline__ void rotate(T ca, T sa, T omc, const T (&n)[3], const
 __device__ __forceinline__ double pair_xor(double x) { return __shfl_xor(x, 1, 64); }
 __device__ __forceinline__ float pair_xor(float x) { return __shfl_xor(x, 1, 64); }
 
-template <int F, bool W, bool M, bool A>
+// Fixed-point cell sums (Sec. III.C, reproducibility): a term x becomes the
+// integer trunc(x 2^80) in 128-bit two's complement; sums are exact, hence
+// independent of the order of the terms, and the value is the integer rounded
+// once to FP64, times 2^-80.  Terms need |x| < 2^37 (no sum of at most 2^10
+// terms can overflow); others (and NaN) set kErrFixRange.
+struct Fix {
+  uint64_t lo, hi;
+};
+__device__ __forceinline__ void fix_add(Fix& a, double x, uint32_t& err) {
+  if (!(fabs(x) < 0x1p37)) {
+    err |= kErrFixRange;
+    return;
+  }
+  const uint64_t bits = (uint64_t)__double_as_longlong(x);
+  const uint32_t ex = (uint32_t)(bits >> 52) & 0x7ffu;
+  uint64_t mant = bits & 0x000fffffffffffffull;
+  if (ex) mant |= 0x0010000000000000ull;
+  // |x| 2^80 = mant 2^sh, sh = max(ex, 1) - 1075 + 80 <= 64 in range
+  const int sh = (int)(ex ? ex : 1u) - 995;
+  uint64_t lo, hi;
+  if (sh >= 64) {
+    lo = 0;
+    hi = mant;
+  } else if (sh > 0) {
+    lo = mant << sh;
+    hi = mant >> (64 - sh);
+  } else {
+    lo = -sh < 64 ? mant >> -sh : 0ull;  // truncation of the magnitude
+    hi = 0;
+  }
+  if (bits >> 63) {
+    lo = ~lo + 1ull;
+    hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+  }
+  const uint64_t nlo = a.lo + lo;
+  a.hi = a.hi + hi + (nlo < lo ? 1ull : 0ull);
+  a.lo = nlo;
+}
+// Exact sum over the lane pair (both lanes hold the total).
+__device__ __forceinline__ void fix_pair(Fix& a) {
+  const uint64_t olo = (uint64_t)__shfl_xor((long long)a.lo, 1, 64);
+  const uint64_t ohi = (uint64_t)__shfl_xor((long long)a.hi, 1, 64);
+  const uint64_t nlo = a.lo + olo;
+  a.hi = a.hi + ohi + (nlo < olo ? 1ull : 0ull);
+  a.lo = nlo;
+}
+// Nearest FP64 of the integer, times 2^-80.  The 128-bit magnitude is
+// normalised so that its top 64 bits carry the rounding position, with the
+// bits below OR-ed into bit 0 (sticky); the u64 -> f64 conversion then rounds
+// to nearest even once.
+__device__ __forceinline__ double fix_value(Fix a) {
+  const bool neg = (int64_t)a.hi < 0;
+  uint64_t lo = a.lo, hi = a.hi;
+  if (neg) {
+    lo = ~lo + 1ull;
+    hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+  }
+  double d;
+  if (hi == 0) {
+    d = (double)lo * 0x1p-80;
+  } else {
+    const int lz = __clzll((long long)hi);
+    const uint64_t top = lz ? (hi << lz) | (lo >> (64 - lz)) : hi;
+    const uint64_t rest = lo << lz;
+    d = ldexp((double)(top | (rest != 0ull ? 1ull : 0ull)), 64 - lz - 80);
+  }
+  return neg ? -d : d;
+}
+
+template <int F, bool W, bool M, bool A, bool X>
 __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd,
                           const PhantomSums* __restrict__ ph,
                           const typename Form<F>::Vs* __restrict__ sv0,
@@ -1023,7 +1092,7 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
                           const typename Form<F>::Xs* __restrict__ sx1,
                           const typename Form<F>::Xs* __restrict__ sx2, const double (&s)[3],
                           uint32_t b, uint32_t e, uint32_t half, bool valid,
-                          typename CellRec<F, A>::T* out) {
+                          typename CellRec<F, A>::T* out, uint32_t& err) {
   const uint32_t nf = valid ? e - b : 0u;
   const uint32_t mid = b + (nf + 1) / 2;
   const uint32_t qb = half ? mid : b, qe = valid ? (half ? e : mid) : b;
@@ -1042,7 +1111,29 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
   const uint32_t ntot = nf + nph;
   const double m = B.mass;
   double V[3];
-  if constexpr (F == kFormSplit) {
+  if constexpr (X) {
+    // fixed-point momentum sums of the FP64 terms m v_i (every form)
+    Fix fp[3] = {{0ull, 0ull}, {0ull, 0ull}, {0ull, 0ull}};
+    for (uint32_t q = qb; q < qe; ++q) {
+      fix_add(fp[0], m * (double)sv0[q], err);
+      fix_add(fp[1], m * (double)sv1[q], err);
+      fix_add(fp[2], m * (double)sv2[q], err);
+    }
+    double P[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      fix_pair(fp[k]);
+      P[k] = fix_value(fp[k]);
+    }
+    if (W && nph) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) P[k] = P[k] + m * pv[k];
+    }
+    const double Mtot = (double)(ntot ? ntot : 1u) * m;
+    V[0] = P[0] / Mtot;
+    V[1] = P[1] / Mtot;
+    V[2] = P[2] / Mtot;
+  } else if constexpr (F == kFormSplit) {
     // compensated FP32 momentum sums (Neumaier)
     const float mf = (float)m;
     float s[3] = {0.f, 0.f, 0.f}, c[3] = {0.f, 0.f, 0.f};
@@ -1103,14 +1194,25 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
   }
   double kappa = 1.0, K = 0.0;
   if (M) {
+    if constexpr (X) {
+      Fix fk = {0ull, 0ull};
+      for (uint32_t q = qb; q < qe; ++q) {
+        const double dx = (double)sv0[q] - V[0], dy = (double)sv1[q] - V[1],
+                     dz = (double)sv2[q] - V[2];
+        fix_add(fk, m * (dx * dx + dy * dy + dz * dz), err);
+      }
+      fix_pair(fk);
+      K = fix_value(fk);
+    } else {
 #pragma unroll 4
-    for (uint32_t q = qb; q < qe; ++q) {
-      const double dx = (double)sv0[q] - V[0], dy = (double)sv1[q] - V[1],
-                   dz = (double)sv2[q] - V[2];
-      K = K + m * (dx * dx + dy * dy + dz * dz);
+      for (uint32_t q = qb; q < qe; ++q) {
+        const double dx = (double)sv0[q] - V[0], dy = (double)sv1[q] - V[1],
+                     dz = (double)sv2[q] - V[2];
+        K = K + m * (dx * dx + dy * dy + dz * dz);
+      }
+      const double oK = pair_xor(K);
+      K = half ? oK + K : K + oK;
     }
-    const double oK = pair_xor(K);
-    K = half ? oK + K : K + oK;
     if (W && nph) {
       // sum over phantoms of m |v - V|^2 from their velocity sums
       const double vV = pv[0] * V[0] + pv[1] * V[1] + pv[2] * V[2];
@@ -1128,15 +1230,29 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
   // omega = 0.  Both lanes of the pair build identical totals.
   double rc[3] = {0.0, 0.0, 0.0}, om[3] = {0.0, 0.0, 0.0};
   if constexpr (A) {
-    for (uint32_t q = qb; q < qe; ++q) {
-      rc[0] = rc[0] + frame_pos(sx0[q], s[0]);
-      rc[1] = rc[1] + frame_pos(sx1[q], s[1]);
-      rc[2] = rc[2] + frame_pos(sx2[q], s[2]);
-    }
+    if constexpr (X) {
+      Fix fr[3] = {{0ull, 0ull}, {0ull, 0ull}, {0ull, 0ull}};
+      for (uint32_t q = qb; q < qe; ++q) {
+        fix_add(fr[0], frame_pos(sx0[q], s[0]), err);
+        fix_add(fr[1], frame_pos(sx1[q], s[1]), err);
+        fix_add(fr[2], frame_pos(sx2[q], s[2]), err);
+      }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double o = pair_xor(rc[k]);
-      rc[k] = (half ? o + rc[k] : rc[k] + o) / (double)(nf ? nf : 1u);
+      for (int k = 0; k < 3; ++k) {
+        fix_pair(fr[k]);
+        rc[k] = fix_value(fr[k]) / (double)(nf ? nf : 1u);
+      }
+    } else {
+      for (uint32_t q = qb; q < qe; ++q) {
+        rc[0] = rc[0] + frame_pos(sx0[q], s[0]);
+        rc[1] = rc[1] + frame_pos(sx1[q], s[1]);
+        rc[2] = rc[2] + frame_pos(sx2[q], s[2]);
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double o = pair_xor(rc[k]);
+        rc[k] = (half ? o + rc[k] : rc[k] + o) / (double)(nf ? nf : 1u);
+      }
     }
     // Moments about the centre of mass: M = sum r_ic u_i^T and S = sum r_ic
     // r_ic^T (15 sums, no per-particle rotation).  Then I = tr(S) 1 - S, the
@@ -1147,6 +1263,44 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
     for (int k = 0; k < 9; ++k) mm[k] = 0.0;
 #pragma unroll
     for (int k = 0; k < 6; ++k) ss[k] = 0.0;
+    if constexpr (X) {
+      // one pass per row a of M, with S_aa and S_a(a+1 mod 3): five exact
+      // sums live at a time
+#pragma unroll 1
+      for (int a = 0; a < 3; ++a) {
+        Fix f5[5] = {{0ull, 0ull}, {0ull, 0ull}, {0ull, 0ull}, {0ull, 0ull}, {0ull, 0ull}};
+        const int a1 = a == 2 ? 0 : a + 1;
+        for (uint32_t q = qb; q < qe; ++q) {
+          const double r[3] = {frame_pos(sx0[q], s[0]) - rc[0], frame_pos(sx1[q], s[1]) - rc[1],
+                               frame_pos(sx2[q], s[2]) - rc[2]};
+          const double u[3] = {(double)sv0[q] - V[0], (double)sv1[q] - V[1],
+                               (double)sv2[q] - V[2]};
+          const double ra = a == 0 ? r[0] : (a == 1 ? r[1] : r[2]);
+          const double rb = a1 == 0 ? r[0] : (a1 == 1 ? r[1] : r[2]);
+          fix_add(f5[0], ra * u[0], err);
+          fix_add(f5[1], ra * u[1], err);
+          fix_add(f5[2], ra * u[2], err);
+          fix_add(f5[3], ra * ra, err);
+          fix_add(f5[4], ra * rb, err);
+        }
+        double v5[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          fix_pair(f5[k]);
+          v5[k] = fix_value(f5[k]);
+        }
+        // scatter into mm / ss (ss: xx, yy, zz, xy, xz, yz; a = 2 gives zx = xz)
+#pragma unroll
+        for (int b2 = 0; b2 < 3; ++b2) {
+          if (a == 0) mm[b2] = v5[b2];
+          if (a == 1) mm[3 + b2] = v5[b2];
+          if (a == 2) mm[6 + b2] = v5[b2];
+        }
+        if (a == 0) { ss[0] = v5[3]; ss[3] = v5[4]; }
+        if (a == 1) { ss[1] = v5[3]; ss[5] = v5[4]; }
+        if (a == 2) { ss[2] = v5[3]; ss[4] = v5[4]; }
+      }
+    } else {
     for (uint32_t q = qb; q < qe; ++q) {
       const double r[3] = {frame_pos(sx0[q], s[0]) - rc[0], frame_pos(sx1[q], s[1]) - rc[1],
                            frame_pos(sx2[q], s[2]) - rc[2]};
@@ -1171,6 +1325,7 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
     for (int k = 0; k < 6; ++k) {
       const double o = pair_xor(ss[k]);
       ss[k] = half ? o + ss[k] : ss[k] + o;
+    }
     }
     const double xx = ss[1] + ss[2], yy = ss[0] + ss[2], zz = ss[0] + ss[1];
     const double xy = -ss[3], xz = -ss[4], yz = -ss[5];
@@ -1284,8 +1439,8 @@ struct TileWalk {
   }
 };
 
-template <int F, bool W, bool M, bool A>
-__global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu((W || A) ? 2 : 3)))
+template <int F, bool W, bool M, bool A, bool X>
+__global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu((W || A || X) ? 2 : 3)))
 void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   using Fm = Form<F>;
   using Vs = typename Fm::Vs;
@@ -1542,10 +1697,10 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
           }
         }
         const double s_t[3] = {s_sh[0], s_sh[1], s_sh[2]};
-        cell_work<F, W, M, A>(B, lkey0 + c, s_sh[2], cd,
-                              W ? d.phs + T.c0 + (valid ? c : 0u) : nullptr, s_v[0], s_v[1],
-                              s_v[2], s_x[0], s_x[1], s_x[2], s_t, b, e, lane & 1u, valid,
-                              &s_cell[j]);
+        cell_work<F, W, M, A, X>(B, lkey0 + c, s_sh[2], cd,
+                                 W ? d.phs + T.c0 + (valid ? c : 0u) : nullptr, s_v[0], s_v[1],
+                                 s_v[2], s_x[0], s_x[1], s_x[2], s_t, b, e, lane & 1u, valid,
+                                 &s_cell[j], err);
       }
       wave_sync();
 
@@ -1573,12 +1728,14 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
               for (int a = 0; a < 3; ++a)
                 v.v[a] = C.V[a] + fmaf(C.R[3 * a], u[0], fmaf(C.R[3 * a + 1], u[1], C.R[3 * a + 2] * u[2]));
               if constexpr (A) {
-                const float r[3] = {(float)frame_pos(s_x[0][q], s_sh[0]) - C.rc[0],
-                                    (float)frame_pos(s_x[1][q], s_sh[1]) - C.rc[1],
-                                    (float)frame_pos(s_x[2][q], s_sh[2]) - C.rc[2]};
-                v.v[0] = v.v[0] + (C.om[1] * r[2] - C.om[2] * r[1]);
-                v.v[1] = v.v[1] + (C.om[2] * r[0] - C.om[0] * r[2]);
-                v.v[2] = v.v[2] + (C.om[0] * r[1] - C.om[1] * r[0]);
+                // omega x r_ic in FP64 (|omega| is large in ill-conditioned
+                // cells), added to the FP32 rotation result with one rounding
+                const double r[3] = {frame_pos(s_x[0][q], s_sh[0]) - C.rc[0],
+                                     frame_pos(s_x[1][q], s_sh[1]) - C.rc[1],
+                                     frame_pos(s_x[2][q], s_sh[2]) - C.rc[2]};
+                v.v[0] = (float)((double)v.v[0] + (C.om[1] * r[2] - C.om[2] * r[1]));
+                v.v[1] = (float)((double)v.v[1] + (C.om[2] * r[0] - C.om[0] * r[2]));
+                v.v[2] = (float)((double)v.v[2] + (C.om[0] * r[1] - C.om[1] * r[0]));
               }
             }
             if (B.grav) {
@@ -1734,38 +1891,57 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   if (err) atomicOr(&d.ctrl->err, err);
 }
 
-template <int F, bool W, bool M, bool A = false>
-static hipError_t occ_of(int* n) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_collide<F, W, M, A>, kCollideThreads, 0);
+// Runtime flags (form, walls, thermostat, SRD+a, fixed-point sums) -> the
+// k_collide instantiation.  SRD+a next to walls is not built.
+struct CollideLaunchOp {
+  template <int F, bool W, bool M, bool A, bool X>
+  static hipError_t run(const Dev& d, const Launch& l, int*) {
+    hipLaunchKernelGGL((k_collide<F, W, M, A, X>), dim3(l.collide_grid), dim3(kCollideThreads), 0,
+                       l.stream, d, (uint32_t)l.ntiles, l.xcd_remap);
+    return hipGetLastError();
+  }
+};
+struct CollideOccOp {
+  template <int F, bool W, bool M, bool A, bool X>
+  static hipError_t run(const Dev&, const Launch&, int* n) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_collide<F, W, M, A, X>,
+                                                        kCollideThreads, 0);
+  }
+};
+template <class Op, int F, bool W, bool M, bool A>
+static hipError_t collide_pick_x(const Dev& d, const Launch& l, int* n) {
+  if constexpr (A && W) {
+    return hipErrorInvalidValue;
+  } else {
+    return l.fixed ? Op::template run<F, W, M, A, true>(d, l, n)
+                   : Op::template run<F, W, M, A, false>(d, l, n);
+  }
+}
+template <class Op, int F, bool W, bool M>
+static hipError_t collide_pick_a(const Dev& d, const Launch& l, int* n) {
+  return l.amc ? collide_pick_x<Op, F, W, M, true>(d, l, n)
+               : collide_pick_x<Op, F, W, M, false>(d, l, n);
+}
+template <class Op, int F, bool W>
+static hipError_t collide_pick_m(const Dev& d, const Launch& l, int* n) {
+  return l.mbs ? collide_pick_a<Op, F, W, true>(d, l, n) : collide_pick_a<Op, F, W, false>(d, l, n);
+}
+template <class Op, int F>
+static hipError_t collide_pick_w(const Dev& d, const Launch& l, int* n) {
+  return l.walls ? collide_pick_m<Op, F, true>(d, l, n) : collide_pick_m<Op, F, false>(d, l, n);
+}
+template <class Op>
+static hipError_t collide_dispatch(const Dev& d, const Launch& l, int* n) {
+  switch (l.form) {
+    case kFormF64: return collide_pick_w<Op, kFormF64>(d, l, n);
+    case kFormF32: return collide_pick_w<Op, kFormF32>(d, l, n);
+    case kFormSplit: return collide_pick_w<Op, kFormSplit>(d, l, n);
+    default: return hipErrorInvalidValue;
+  }
 }
 
-hipError_t collide_occupancy(int form, int walls, int mbs, int amc, int* blocks_per_cu) {
-  if (amc) {
-    if (walls) return hipErrorInvalidValue;
-    switch (form * 2 + (mbs ? 1 : 0)) {
-      case 0: return occ_of<kFormF64, false, false, true>(blocks_per_cu);
-      case 1: return occ_of<kFormF64, false, true, true>(blocks_per_cu);
-      case 2: return occ_of<kFormF32, false, false, true>(blocks_per_cu);
-      case 3: return occ_of<kFormF32, false, true, true>(blocks_per_cu);
-      case 4: return occ_of<kFormSplit, false, false, true>(blocks_per_cu);
-      default: return occ_of<kFormSplit, false, true, true>(blocks_per_cu);
-    }
-  }
-  const int sel = form * 4 + (walls ? 2 : 0) + (mbs ? 1 : 0);
-  switch (sel) {
-    case 0: return occ_of<kFormF64, false, false>(blocks_per_cu);
-    case 1: return occ_of<kFormF64, false, true>(blocks_per_cu);
-    case 2: return occ_of<kFormF64, true, false>(blocks_per_cu);
-    case 3: return occ_of<kFormF64, true, true>(blocks_per_cu);
-    case 4: return occ_of<kFormF32, false, false>(blocks_per_cu);
-    case 5: return occ_of<kFormF32, false, true>(blocks_per_cu);
-    case 6: return occ_of<kFormF32, true, false>(blocks_per_cu);
-    case 7: return occ_of<kFormF32, true, true>(blocks_per_cu);
-    case 8: return occ_of<kFormSplit, false, false>(blocks_per_cu);
-    case 9: return occ_of<kFormSplit, false, true>(blocks_per_cu);
-    case 10: return occ_of<kFormSplit, true, false>(blocks_per_cu);
-    default: return occ_of<kFormSplit, true, true>(blocks_per_cu);
-  }
+hipError_t collide_occupancy(const Launch& l, int* blocks_per_cu) {
+  return collide_dispatch<CollideOccOp>(Dev{}, l, blocks_per_cu);
 }
 
 // ---------------------------------------------------------------------------
@@ -2025,44 +2201,7 @@ hipError_t launch_scatter(const Dev& d, const Launch& l) {
 
 hipError_t launch_collide(const Dev& d, const Launch& l) {
   if (l.ntiles == 0) return hipSuccess;
-  const dim3 g(l.collide_grid), b(kCollideThreads);
-  const uint32_t nt = l.ntiles;
-  const int xr = l.xcd_remap;
-  if (l.amc) {
-    if (l.walls) return hipErrorInvalidValue;
-    switch (l.form * 2 + (l.mbs ? 1 : 0)) {
-#define MPC_AMC_CASE(n, F, M) \
-  case n: hipLaunchKernelGGL((k_collide<F, false, M, true>), g, b, 0, l.stream, d, nt, xr); break;
-      MPC_AMC_CASE(0, kFormF64, false)
-      MPC_AMC_CASE(1, kFormF64, true)
-      MPC_AMC_CASE(2, kFormF32, false)
-      MPC_AMC_CASE(3, kFormF32, true)
-      MPC_AMC_CASE(4, kFormSplit, false)
-      MPC_AMC_CASE(5, kFormSplit, true)
-#undef MPC_AMC_CASE
-      default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-  }
-  switch (l.form * 4 + (l.walls ? 2 : 0) + (l.mbs ? 1 : 0)) {
-#define MPC_COLLIDE_CASE(n, F, W, M) \
-  case n: hipLaunchKernelGGL((k_collide<F, W, M, false>), g, b, 0, l.stream, d, nt, xr); break;
-    MPC_COLLIDE_CASE(0, kFormF64, false, false)
-    MPC_COLLIDE_CASE(1, kFormF64, false, true)
-    MPC_COLLIDE_CASE(2, kFormF64, true, false)
-    MPC_COLLIDE_CASE(3, kFormF64, true, true)
-    MPC_COLLIDE_CASE(4, kFormF32, false, false)
-    MPC_COLLIDE_CASE(5, kFormF32, false, true)
-    MPC_COLLIDE_CASE(6, kFormF32, true, false)
-    MPC_COLLIDE_CASE(7, kFormF32, true, true)
-    MPC_COLLIDE_CASE(8, kFormSplit, false, false)
-    MPC_COLLIDE_CASE(9, kFormSplit, false, true)
-    MPC_COLLIDE_CASE(10, kFormSplit, true, false)
-    MPC_COLLIDE_CASE(11, kFormSplit, true, true)
-#undef MPC_COLLIDE_CASE
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return collide_dispatch<CollideLaunchOp>(d, l, nullptr);
 }
 
 hipError_t launch_canon_perm(const Dev& d, const Launch& l, const uint32_t* ids) {

@@ -80,5 +80,5 @@ def test_amc_flag_validation_on_host():
         m.workspace_bytes(m.make_params(dict(c1, amc=True, walls=True)))
     assert e.value.code == m.EINVAL
     with pytest.raises(m.MPCError) as e:
-        m.workspace_bytes(m.make_params(c1, flags=8))
+        m.workspace_bytes(m.make_params(c1, flags=16))
     assert e.value.code == m.EINVAL
