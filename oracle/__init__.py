@@ -38,9 +38,10 @@ def build(out: str = LIB_PATH, src: str = _SRC) -> str:
 
 class _Params(C.Structure):
     _fields_ = [("L", C.c_int32 * 3), ("walls", C.c_int32), ("mbs", C.c_int32),
-                ("amc", C.c_int32), ("fixed", C.c_int32), ("h", C.c_double), ("alpha", C.c_double),
+                ("amc", C.c_int32), ("fixed", C.c_int32), ("slip", C.c_int32),
+                ("h", C.c_double), ("alpha", C.c_double),
                 ("kT", C.c_double), ("mass", C.c_double), ("density", C.c_double),
-                ("g", C.c_double * 3), ("seed", C.c_uint64)]
+                ("g", C.c_double * 3), ("seed", C.c_uint64), ("uwall", C.c_double)]
 
 
 @dataclass
@@ -57,6 +58,8 @@ class Params:
     walls: bool = False
     amc: bool = False
     fixed: bool = False
+    slip: bool = False
+    uwall: float = 0.0
     g: tuple = field(default_factory=lambda: (0.0, 0.0, 0.0))
 
     def c(self) -> _Params:
@@ -64,6 +67,8 @@ class Params:
         p.L[:] = [int(v) for v in self.L]
         p.walls, p.mbs, p.amc = int(self.walls), int(self.mbs), int(self.amc)
         p.fixed = int(self.fixed)
+        p.slip = int(self.slip)
+        p.uwall = float(self.uwall)
         p.h, p.alpha, p.kT, p.mass = self.h, self.alpha, self.kT, self.mass
         p.density = self.density
         p.g[:] = [float(v) for v in self.g]

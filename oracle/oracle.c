@@ -103,7 +103,10 @@ static double wrap(double x, double L) {
 /* Sec. II Eq.(1): r <- r + h v.  No-slip walls (Sec. II, Boundary            */
 /* conditions): a particle that crossed z = 0 or z = H is put back by         */
 /* time-reversed bounce-back, r <- r_end - 2 v t_rem, v <- -v, where t_rem is */
-/* the time spent beyond the wall (reading: bounce-back geometry).            */
+/* the time spent beyond the wall (reading: bounce-back geometry).  A moving  */
+/* wall (velocity u along x) reverses the velocity in its own frame:          */
+/* v <- 2u - v, r <- r_end - 2 (v - u) t_rem.  Slip walls reflect            */
+/* specularly: only v_z and z are mirrored.                                   */
 /* ------------------------------------------------------------------------ */
 int64_t orc_stream(const orc_params* p, int64_t n, double* x, double* v) {
   const double h = p->h;
@@ -126,13 +129,18 @@ int64_t orc_stream(const orc_params* p, int64_t n, double* x, double* v) {
       if (crossed) {
         double vz = v[2 * n + i];
         double tr2 = 2.0 * ((ze - zw) / vz);
-        xe = xe - tr2 * v[i];
-        ye = ye - tr2 * v[n + i];
-        ze = ze - tr2 * vz;
+        if (p->slip) {
+          ze = ze - tr2 * vz;
+        } else {
+          double uw = zw == 0.0 ? -p->uwall : p->uwall;
+          xe = xe - tr2 * (v[i] - uw);
+          ye = ye - tr2 * v[n + i];
+          ze = ze - tr2 * vz;
+          v[i] = 2.0 * uw - v[i];
+          v[n + i] = -v[n + i];
+        }
         if (ze < 0.0) ze = 0.0;
         if (ze > Lz) ze = Lz;
-        v[i] = -v[i];
-        v[n + i] = -v[n + i];
         v[2 * n + i] = -v[2 * n + i];
         ++bounces;
       }
@@ -497,10 +505,17 @@ int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, dou
     if (nf == 0) continue;
 
     int32_t np = 0;
-    if (p->walls) {
+    if (p->walls && !p->slip) {
       int32_t cz = (int32_t)(c / plane) - 1;
       double fw = orc_wall_fraction(p, s[2], cz);
-      if (fw > 0.0) np = orc_phantoms(p, t, (uint32_t)c, fw, vp, PMAX);
+      if (fw > 0.0) {
+        np = orc_phantoms(p, t, (uint32_t)c, fw, vp, PMAX);
+        /* phantoms move with the wall whose part of the cell they fill: the
+         * layer cut by z = 0 is c_z = 0 (s_z >= 0) or c_z = -1 (s_z < 0) */
+        int32_t bottom = cz == (s[2] >= 0.0 ? 0 : -1);
+        double uw = bottom ? -p->uwall : p->uwall;
+        for (int32_t q = 0; q < np; ++q) vp[3 * q] = vp[3 * q] + uw;
+      }
     }
     int64_t ntot = nf + np;
 

@@ -40,6 +40,8 @@ typedef struct {
                          correction                                            */
   int32_t  fixed;     /* 1: cell sums of fluid terms in fixed point (Sec.
                          III.C, reproducibility): independent of the order  */
+  int32_t  slip;      /* with walls, 1: slip walls (specular reflection, no
+                         phantom particles) instead of no-slip walls         */
   double   h;         /* MPC time step                                         */
   double   alpha;     /* rotation angle, radians                               */
   double   kT;        /* k_B T                                                 */
@@ -47,6 +49,8 @@ typedef struct {
   double   density;   /* <N_c>, mean particles per cell (phantom fill)         */
   double   g[3];      /* constant acceleration (gravity), applied as a kick    */
   uint64_t seed;      /* Philox key                                            */
+  double   uwall;     /* no-slip walls: the wall at z = H moves with velocity
+                         +uwall along x, the wall at z = 0 with -uwall      */
 } orc_params;
 
 /* Per-cell diagnostics written by orc_collide when cell_out != NULL

@@ -25,7 +25,15 @@ MUTANTS = {
     "stream_dropped_h": ("double xe = fma(h, v[i], x[i]);", "double xe = v[i] + x[i];"),
     "stream_sign": ("double ye = fma(h, v[n + i], x[n + i]);", "double ye = fma(-h, v[n + i], x[n + i]);"),
     "wrap_wrong_branch": ("    x = x + L;\n  } else if (x >= L) {", "    x = x - L;\n  } else if (x >= L) {"),
-    "bounce_keeps_vx": ("        v[i] = -v[i];\n", "        v[i] = v[i];\n"),
+    "bounce_keeps_vx": ("v[i] = 2.0 * uw - v[i];", "v[i] = 2.0 * uw + v[i];"),
+    "wall_frame_ignored": ("xe = xe - tr2 * (v[i] - uw);", "xe = xe - tr2 * v[i];"),
+    "wall_velocity_sign": ("double uw = zw == 0.0 ? -p->uwall : p->uwall;",
+                           "double uw = zw == 0.0 ? p->uwall : -p->uwall;"),
+    "slip_mirrors_all": ("        if (p->slip) {\n          ze = ze - tr2 * vz;\n        } else {",
+                         "        if (0) {\n          ze = ze - tr2 * vz;\n        } else {"),
+    "slip_keeps_phantoms": ("if (p->walls && !p->slip) {", "if (p->walls) {"),
+    "phantom_wall_velocity": ("for (int32_t q = 0; q < np; ++q) vp[3 * q] = vp[3 * q] + uw;",
+                              "for (int32_t q = 0; q < np; ++q) vp[3 * q] = vp[3 * q] - uw;"),
     "bounce_mirror_factor": ("double tr2 = 2.0 * ((ze - zw) / vz);", "double tr2 = 1.0 * ((ze - zw) / vz);"),
     "keys_truncate": ("c[k] = (int64_t)floor(y);", "c[k] = (int64_t)y;"),
     "keys_y_fastest": ("key[i] = (uint32_t)((c[2] * p->L[1] + c[1]) * p->L[0] + c[0]);",
@@ -73,6 +81,8 @@ FAST_PINS = [
     "test_amc_conserves_angular_momentum", "test_amc_correction_is_rigid_rotation",
     "test_amc_alpha_zero_is_identity", "test_amc_refused_with_walls", "test_amc_with_thermostat",
     "test_fixed_sums_exact", "test_fixed_sums_order_independent", "test_fixed_sums_range",
+    "test_moving_wall_bounce_is_galilean", "test_slip_walls_reflect_specularly",
+    "test_slip_walls_exert_no_tangential_force", "test_couette_profile",
 ]
 
 PARAMS = {"test_keys_exact_floor": [{"walls": False}, {"walls": True}],

@@ -753,3 +753,99 @@ def test_fixed_sums_range(orc):
         refused = True
     assert refused
     orc.step(orc.Params(L=L), 0, x, v)
+
+
+# --- slip walls and moving no-slip walls (Sec. II, Boundary conditions) -------
+def test_moving_wall_bounce_is_galilean(orc):
+    """A no-slip wall moving with velocity u along x bounces particles as a wall
+    at rest does in the wall's own frame (Galilean invariance): streaming with
+    the moving wall equals streaming v - u past a resting wall, shifted back by
+    u h and u.  The wall at z = H moves with +U, the wall at z = 0 with -U."""
+    L = (8, 8, 6)
+    U = 0.7
+    x, v = synth.box_state(L, n=5000, seed=19)
+    v *= 3.0
+    pm = orc.Params(L=L, h=0.5, walls=True, uwall=U)
+    ps = orc.Params(L=L, h=0.5, walls=True)
+    x2, v2, nb = orc.stream(pm, x, v)
+    zend = x[2] + pm.h * v[2]
+    for sel, u in ((zend < 0, -U), (zend > L[2], U)):
+        assert sel.sum() > 50
+        shift = np.array([u, 0.0, 0.0])[:, None]
+        xr, vr, _ = orc.stream(ps, x[:, sel], v[:, sel] - shift)
+        np.testing.assert_allclose(v2[:, sel], vr + shift, rtol=0, atol=1e-14)
+        xe = xr + pm.h * shift
+        d = np.abs(x2[:, sel] - xe)
+        d[0] = d[0] % L[0]
+        d[0] = np.minimum(d[0], L[0] - d[0])
+        assert d.max() < 1e-12
+    rest = (zend >= 0) & (zend <= L[2])
+    xs, vs, _ = orc.stream(ps, x[:, rest], v[:, rest])
+    np.testing.assert_array_equal(x2[:, rest], xs)
+    np.testing.assert_array_equal(v2[:, rest], vs)
+
+
+def test_slip_walls_reflect_specularly(orc):
+    """Slip walls: a crossing particle is mirrored in z (z -> -z_end or
+    2H - z_end) with v_z reversed; x, y and v_x, v_y are those of free
+    flight."""
+    L = (8, 8, 6)
+    p = orc.Params(L=L, h=0.5, walls=True, slip=True)
+    x, v = synth.box_state(L, n=5000, seed=29)
+    v *= 3.0
+    x2, v2, nb = orc.stream(p, x, v)
+    zend = x[2] + p.h * v[2]
+    bot, top = zend < 0, zend > L[2]
+    assert nb == int((bot | top).sum()) > 100
+    np.testing.assert_allclose(x2[2, bot], -zend[bot], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(x2[2, top], 2 * L[2] - zend[top], rtol=0, atol=1e-13)
+    np.testing.assert_array_equal(v2[:2], v[:2])
+    np.testing.assert_array_equal(v2[2, bot | top], -v[2, bot | top])
+    free = orc.Params(L=(8, 8, 6), h=0.5)
+    xf, _, _ = orc.stream(free, x, v)
+    np.testing.assert_array_equal(x2[:2], xf[:2])
+
+
+def test_slip_walls_exert_no_tangential_force(orc):
+    """With slip walls (no phantoms) a body force g along x raises the total
+    momentum by N m g h per step exactly (to rounding); no-slip walls exchange
+    momentum with the fluid."""
+    L = (6, 6, 8)
+    x, v = synth.box_state(L, seed=37)
+    n = x.shape[1]
+    g = 0.01
+    out = {}
+    for slip in (True, False):
+        p = orc.Params(L=L, walls=True, slip=slip, mbs=True, g=(g, 0.0, 0.0), seed=3)
+        x1, v1 = orc.run(p, x, v, 30)
+        out[slip] = v1[0].sum() - v[0].sum()
+    expect = n * g * 0.1 * 30
+    assert abs(out[True] - expect) < 1e-9 * n
+    assert abs(out[False] - expect) > 1.0
+
+
+def test_couette_profile(orc):
+    """No-slip walls moving with +-U along x: the time-averaged steady profile
+    v_x(z) is linear through zero at mid-height with slope close to 2U/H (the
+    phantoms keep the slip at the walls small)."""
+    L = (6, 6, 10)
+    U = 0.5
+    p = orc.Params(L=L, walls=True, mbs=True, uwall=U, seed=11)
+    x, v = synth.box_state(L, seed=45)
+    x, v = orc.run(p, x, v, 500)
+    nb = 20
+    acc = np.zeros(nb)
+    cnt = np.zeros(nb)
+    for t in range(500, 1700, 4):
+        x, v = orc.run(p, x, v, 4, t0=t)
+        b = np.minimum((x[2] / L[2] * nb).astype(int), nb - 1)
+        acc += np.bincount(b, v[0], nb)
+        cnt += np.bincount(b, minlength=nb)
+    z = (np.arange(nb) + 0.5) * L[2] / nb
+    prof = acc / cnt
+    slope, icpt = np.polyfit(z - L[2] / 2, prof, 1)
+    resid = prof - (slope * (z - L[2] / 2) + icpt)
+    r2 = 1 - (resid ** 2).sum() / ((prof - prof.mean()) ** 2).sum()
+    print(f"Couette: slope {slope:.4f} (2U/H = {2 * U / L[2]:.4f}), intercept {icpt:.4f}, R2 {r2:.4f}")
+    assert abs(slope / (2 * U / L[2]) - 1) < 0.1
+    assert abs(icpt) < 0.02 and r2 > 0.98
