@@ -13,8 +13,9 @@ timed region; 200 steps by default).  The same line carries:
   forms        : FP32 and split-FP32 on the same box, FP64 stored in cell
                  order after every step, the batched ensemble of 64
                  uneven boxes (graph replay), the angular-momentum-
-                 conserving collision SRD+a in FP64 and split-FP32, and FP64
-                 with fixed-point (order-independent) cell sums;
+                 conserving collision SRD+a in FP64 and split-FP32, FP64
+                 with fixed-point (order-independent) cell sums, and the
+                 256x256x64 channel with slip walls or moving walls;
   cpu_baseline : the single-threaded CPU oracle on a bounded sample.
 --copy-probe-gib G adds one device-to-device copy of G GiB before the run: the
 counter runs use it to scale FETCH_SIZE / WRITE_SIZE to bytes.
@@ -227,7 +228,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--forms",
-                    default="fp32,split,fp64_sorted_every_step,batched,amc,amc_split,fp64_fixed",
+                    default="fp32,split,fp64_sorted_every_step,batched,amc,amc_split,fp64_fixed,"
+                            "walls_slip,walls_couette",
                     help="extra entries besides the FP64 headline (comma list, or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=500)
@@ -326,6 +328,27 @@ def main():
                     "collide_ms": c2,
                     "collide_achieved_GBs": n2 * 2 * STATE_BYTES["fp64"] / (c2 * 1e-3) / 1e9}
                 print(f"[fp64 R=1 C2] {w2 * 1e3 / args.steps:.3f} ms/step collide {c2:.3f} ms",
+                      file=sys.stderr)
+            elif form in ("walls_slip", "walls_couette"):
+                # the 256 x 256 x 64 channel, FP64, thermostat: slip walls with a
+                # body force, or no-slip walls moving with +-0.1 (shear flow)
+                c5 = synth.config("C5")
+                wbox = (dict(c5, slip=True) if form == "walls_slip"
+                        else dict(c5, g=(0.0, 0.0, 0.0), uwall=0.1))
+                n2, w2, k2, o2 = run_box(mpc, torch, wbox, "fp64", R, args.steps, args.warmup)
+                v2 = n2 * args.steps / w2
+                c2 = k2.collide_ms / max(1, k2.collide_launches)
+                forms[form] = {
+                    "workload": ("256x256x64 channel, FP64, thermostat, " +
+                                 ("slip walls, g = 1e-3" if form == "walls_slip"
+                                  else "no-slip walls moving with +-0.1 along x")
+                                 + f", reorder every {R} steps"),
+                    "value": v2, "unit": "particle-steps/s",
+                    "ms_per_step": w2 * 1e3 / args.steps,
+                    "collide_ms": c2,
+                    "collide_achieved_GBs": n2 * 2 * STATE_BYTES["fp64"] / (c2 * 1e-3) / 1e9,
+                    "launch": run_box.last_tiling}
+                print(f"[{form}] N={n2} {w2 * 1e3 / args.steps:.3f} ms/step collide {c2:.3f} ms",
                       file=sys.stderr)
             elif form == "fp64_fixed":
                 fbox = dict(box, fixed=True)

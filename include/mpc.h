@@ -75,6 +75,9 @@ enum {
                        D u_i + omega x r_ic so that their kinetic energy equals the
                        drawn E_k (angular momentum is then scaled by kappa).
                        Periodic boxes only: with MPC_WALLS_Z -> MPC_EINVAL           */
+  MPC_SLIP = 16u,    /* with MPC_WALLS_Z: slip walls (Sec. II, Boundary conditions):
+                       specular reflection (z and v_z mirrored, v_x, v_y kept) and no
+                       phantom particles.  Without MPC_WALLS_Z -> MPC_EINVAL         */
   MPC_FIXED_SUMS = 8u /* reproducible cell sums (Sec. III.C): every sum over a cell's
                        fluid particles (momentum, kinetic energy, the SRD+a moments)
                        is exact in fixed point -- each FP64 term x becomes the
@@ -107,8 +110,8 @@ enum {
 typedef struct {
   int32_t  L[3];          /* box in cells; with MPC_WALLS_Z, L[2] = H                     */
   int32_t  form;          /* mpc_form (same for all boxes)                                 */
-  uint32_t flags;         /* MPC_MBS | MPC_WALLS_Z | MPC_AMC | MPC_FIXED_SUMS (same for
-                             all boxes)                                                   */
+  uint32_t flags;         /* MPC_MBS | MPC_WALLS_Z | MPC_SLIP | MPC_AMC | MPC_FIXED_SUMS
+                             (same for all boxes)                                         */
   int32_t  reorder_every; /* R: renumber particles in (cell, index) order after every
                              R-th step; 0 = never (same for all boxes)                    */
   double   a;             /* cell size, > 0                                                */
@@ -119,6 +122,9 @@ typedef struct {
   double   mass;          /* particle mass m, > 0                                          */
   double   g[3];          /* constant acceleration; applied as v += g h after collision   */
   uint64_t seed;          /* key of the counter-based random streams                      */
+  double   wall_u;        /* no-slip walls (MPC_WALLS_Z without MPC_SLIP): the wall at
+                             z = H moves with velocity +wall_u along x and the wall at
+                             z = 0 with -wall_u (shear flow); 0 otherwise            */
 } mpc_params;
 
 /* Observables of one box (FP64, compensated sums over the particles). */

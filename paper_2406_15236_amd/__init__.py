@@ -19,7 +19,7 @@ import numpy as np
 from .build import LIB
 
 FP64, FP32, SPLIT32 = 0, 1, 2
-MBS, WALLS_Z, AMC, FIXED_SUMS = 1, 2, 4, 8
+MBS, WALLS_Z, AMC, FIXED_SUMS, SLIP = 1, 2, 4, 8, 16
 FORMS = {"fp64": FP64, "fp32": FP32, "split": SPLIT32}
 MAX_CELL_PARTICLES = 1024
 
@@ -36,7 +36,8 @@ class Params(C.Structure):
     _fields_ = [("L", C.c_int32 * 3), ("form", C.c_int32), ("flags", C.c_uint32),
                 ("reorder_every", C.c_int32), ("a", C.c_double), ("density", C.c_double),
                 ("dt", C.c_double), ("alpha", C.c_double), ("kT", C.c_double),
-                ("mass", C.c_double), ("g", C.c_double * 3), ("seed", C.c_uint64)]
+                ("mass", C.c_double), ("g", C.c_double * 3), ("seed", C.c_uint64),
+                ("wall_u", C.c_double)]
 
 
 class Obs(C.Structure):
@@ -123,7 +124,8 @@ def make_params(box: dict, form="fp64", flags: int | None = None, reorder_every:
     p.form = FORMS[form] if isinstance(form, str) else int(form)
     if flags is None:
         flags = ((MBS if box.get("mbs") else 0) | (WALLS_Z if box.get("walls") else 0)
-                 | (AMC if box.get("amc") else 0) | (FIXED_SUMS if box.get("fixed") else 0))
+                 | (AMC if box.get("amc") else 0) | (FIXED_SUMS if box.get("fixed") else 0)
+                 | (SLIP if box.get("slip") else 0))
     p.flags = int(flags)
     p.reorder_every = int(reorder_every)
     p.a = float(box.get("a", a))
@@ -134,6 +136,7 @@ def make_params(box: dict, form="fp64", flags: int | None = None, reorder_every:
     p.mass = float(box.get("mass", 1.0))
     p.g[:] = [float(v) for v in box.get("g", (0.0, 0.0, 0.0))]
     p.seed = int(box.get("seed", 1)) & 0xFFFFFFFFFFFFFFFF
+    p.wall_u = float(box.get("uwall", 0.0))
     return p
 
 

@@ -58,8 +58,12 @@ int validate(const mpc_params* p, int32_t nbox, std::string* why) {
       return MPC_EINVAL;
     };
     if (q.form < MPC_FP64 || q.form > MPC_SPLIT32) return bad("unknown form");
-    if (q.flags & ~(uint32_t)(MPC_MBS | MPC_WALLS_Z | MPC_AMC | MPC_FIXED_SUMS))
+    if (q.flags & ~(uint32_t)(MPC_MBS | MPC_WALLS_Z | MPC_SLIP | MPC_AMC | MPC_FIXED_SUMS))
       return bad("unknown flags");
+    if ((q.flags & MPC_SLIP) && !(q.flags & MPC_WALLS_Z)) return bad("MPC_SLIP needs MPC_WALLS_Z");
+    if (!isfinite(q.wall_u)) return bad("wall_u must be finite");
+    if (q.wall_u != 0.0 && (!(q.flags & MPC_WALLS_Z) || (q.flags & MPC_SLIP)))
+      return bad("wall_u needs no-slip walls (MPC_WALLS_Z without MPC_SLIP)");
     if ((q.flags & MPC_AMC) && (q.flags & MPC_WALLS_Z))
       return bad("MPC_AMC is defined for periodic boxes (no MPC_WALLS_Z)");
     if (q.form != p[0].form || q.flags != p[0].flags || q.reorder_every != p[0].reorder_every)
@@ -512,6 +516,9 @@ int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
     B.wcbase = (uint32_t)wcb;
     if (B.walls) wcb += 2ull * (uint64_t)q.L[0] * (uint64_t)q.L[1];
     for (int k = 0; k < 3; ++k) B.gh[k] = (q.g[k] / q.a) * q.dt;
+    B.slip = (B.walls && (q.flags & MPC_SLIP)) ? 1u : 0u;
+    B.uw = q.wall_u / q.a;
+    B.uwf = (float)B.uw;
     s->boxes.push_back(B);
     for (uint64_t p0 = 0; p0 < P.box[b].n; p0 += kPartBlock)
       s->pblocks.push_back(PBlock{(uint32_t)b, (uint32_t)(pb + p0)});

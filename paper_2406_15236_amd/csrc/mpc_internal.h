@@ -44,6 +44,10 @@ struct BoxDev {
   uint32_t grav;
   uint32_t wcbase;     // walls: first index of this box's cells of the two
                        // wall-cut layers (2 L0 L1 per box) in a flat index space
+  uint32_t slip;       // walls: specular reflection, no phantoms
+  float uwf;           // uw as float
+  double uw;           // no-slip walls: x velocity of the wall at z = H (cells per
+                       // unit time); the wall at z = 0 moves with -uw
 };
 
 struct Tile {          // one collide work item: cells [c0, c0 + nc) of box `box`

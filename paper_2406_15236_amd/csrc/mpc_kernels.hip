@@ -205,13 +205,18 @@ __device__ __forceinline__ void stream_f64(double (&x)[3], double (&v)[3], BoxRe
     if (lo || hi) {
       const double zw = lo ? 0.0 : H;
       const double tr2 = 2.0 * ((ze - zw) / v[2]);
-      xe = xe - tr2 * v[0];
-      ye = ye - tr2 * v[1];
-      ze = ze - tr2 * v[2];
+      if (B.slip) {  // specular reflection
+        ze = ze - tr2 * v[2];
+      } else {       // bounce-back in the frame of the (moving) wall
+        const double uw = lo ? -B.uw : B.uw;
+        xe = xe - tr2 * (v[0] - uw);
+        ye = ye - tr2 * v[1];
+        ze = ze - tr2 * v[2];
+        v[0] = 2.0 * uw - v[0];
+        v[1] = -v[1];
+      }
       if (ze < 0.0) ze = 0.0;
       if (ze > H) ze = H;
-      v[0] = -v[0];
-      v[1] = -v[1];
       v[2] = -v[2];
     }
   } else {
@@ -233,13 +238,18 @@ __device__ __forceinline__ void stream_f32(float (&x)[3], float (&v)[3], BoxRef 
     if (lo || hi) {
       const float zw = lo ? 0.0f : H;
       const float tr2 = 2.0f * ((ze - zw) / v[2]);
-      xe = xe - tr2 * v[0];
-      ye = ye - tr2 * v[1];
-      ze = ze - tr2 * v[2];
+      if (B.slip) {
+        ze = ze - tr2 * v[2];
+      } else {
+        const float uw = lo ? -B.uwf : B.uwf;
+        xe = xe - tr2 * (v[0] - uw);
+        ye = ye - tr2 * v[1];
+        ze = ze - tr2 * v[2];
+        v[0] = 2.0f * uw - v[0];
+        v[1] = -v[1];
+      }
       if (ze < 0.0f) ze = 0.0f;
       if (ze > H) ze = H;
-      v[0] = -v[0];
-      v[1] = -v[1];
       v[2] = -v[2];
     }
   } else {
@@ -313,14 +323,21 @@ __device__ __forceinline__ void stream_split(uint32_t& cell, float (&o)[3], floa
       for (int k = 0; k < 3; ++k) xe[k] = fma(B.h, vd[k], xd[k]);
       const double Hd = B.Ld[2];
       if (xe[2] < 0.0 || xe[2] > Hd) {
-        const double zw = xe[2] < 0.0 ? 0.0 : Hd;
+        const bool lo = xe[2] < 0.0;
+        const double zw = lo ? 0.0 : Hd;
         const double tr2 = 2.0 * ((xe[2] - zw) / vd[2]);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) xe[k] = xe[k] - tr2 * vd[k];
+        if (B.slip) {
+          xe[2] = xe[2] - tr2 * vd[2];
+        } else {
+          const double uw = lo ? -B.uw : B.uw;
+          xe[0] = xe[0] - tr2 * (vd[0] - uw);
+          xe[1] = xe[1] - tr2 * vd[1];
+          xe[2] = xe[2] - tr2 * vd[2];
+          v[0] = (float)(2.0 * uw - vd[0]);
+          v[1] = -v[1];
+        }
         if (xe[2] < 0.0) xe[2] = 0.0;
         if (xe[2] > Hd) xe[2] = Hd;
-        v[0] = -v[0];
-        v[1] = -v[1];
         v[2] = -v[2];
       }
       xe[0] = wrap64(xe[0], B.Ld[0]);
@@ -733,7 +750,7 @@ template <bool W, bool M>
 __device__ __forceinline__ void cell_draws(BoxRef B, uint64_t t, uint32_t lkey, uint32_t nf,
                                            double sz, CellDraw& out) {
   uint32_t ntot = nf;
-  if (W) {
+  if (W && !B.slip) {
     const int cz = (int)(lkey / (uint32_t)(B.L[0] * B.L[1])) - 1;
     const double fw = wall_fraction(sz, cz, B.L[2]);
     if (fw > 0.0) ntot += (uint32_t)phantom_count(B, t, lkey, fw);
@@ -838,6 +855,7 @@ __global__ __launch_bounds__(kThreads) void k_phantom_sums(Dev d, uint32_t nbox,
     }
   }
   BoxRef B = as_const(d.boxes)[lo];
+  if (B.slip) return;  // slip walls carry no phantoms
   const uint64_t t = as_const(d.ctrl)->step;
   double sh[3];
   shift_of(B, t, sh);
@@ -858,11 +876,14 @@ __global__ __launch_bounds__(kThreads) void k_phantom_sums(Dev d, uint32_t nbox,
   ps.v2 = 0.0;
   PhantomCache pc;
   pc.j = 0xffffffffu;
+  // phantoms move with the wall that fills their part of the cell
+  const double uw = top ? B.uw : -B.uw;
 #pragma unroll 1
   for (int q = 0; q < nph; ++q) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       double vp = B.sd * phantom_normal(B, t, lkey, 3 * q + k, pc);
+      if (k == 0) vp = vp + uw;
       if (round32) vp = (double)(float)vp;
       ps.v[k] = ps.v[k] + vp;
       ps.v2 = ps.v2 + vp * vp;
@@ -1098,7 +1119,7 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
   const uint32_t qb = half ? mid : b, qe = valid ? (half ? e : mid) : b;
   uint32_t nph = 0;
   double pv[3] = {0.0, 0.0, 0.0}, pv2 = 0.0;
-  if (W && valid && nf > 0) {
+  if (W && !B.slip && valid && nf > 0) {
     const int cz = (int)(lkey / (uint32_t)(B.L[0] * B.L[1])) - 1;
     if (wall_fraction(sz, cz, B.L[2]) > 0.0) {
       nph = (uint32_t)ph->n;
