@@ -14,8 +14,10 @@ timed region; 200 steps by default).  The same line carries:
                  order after every step, the batched ensemble of 64
                  uneven boxes (graph replay), the angular-momentum-
                  conserving collision SRD+a in FP64 and split-FP32, FP64
-                 with fixed-point (order-independent) cell sums, and the
-                 256x256x64 channel with slip walls or moving walls;
+                 with fixed-point (order-independent) cell sums, the
+                 256x256x64 channel with slip walls or moving walls, the
+                 cost of each collision feature on 100^3 and the reorder-
+                 interval sweep on 128^3;
   cpu_baseline : the single-threaded CPU oracle on a bounded sample.
 --copy-probe-gib G adds one device-to-device copy of G GiB before the run: the
 counter runs use it to scale FETCH_SIZE / WRITE_SIZE to bytes.
@@ -195,6 +197,45 @@ def run_c5(mpc, torch, synth, steps: int):
             "eta_theory": eta, "tiling": tiling, "profile": [round(float(q), 5) for q in prof]}
 
 
+def run_features(mpc, torch, synth, steps: int = 1000):
+    """Time per step and per kernel against the collision features (plain
+    SRD, + MBS, SRD+a, SRD+a + MBS) on the 100^3 box with 10 particles per
+    cell, FP64, 1000 steps each: the analog of the paper's feature-cost figure
+    (Sec. III.D)."""
+    out = {}
+    base = dict(synth.config("C1"), L=(100, 100, 100))
+    for name, kw in (("plain", {}), ("mbs", {"mbs": True}), ("amc", {"amc": True}),
+                     ("amc_mbs", {"amc": True, "mbs": True})):
+        n, wall, kt, obs = run_box(mpc, torch, dict(base, **kw), "fp64", 20, steps, 10)
+        out[name] = {"ms_per_step": wall * 1e3 / steps,
+                     "scan_draws_ms": kt.scan_ms / steps, "scatter_ms": kt.scatter_ms / steps,
+                     "collide_ms": kt.collide_ms / steps, "advance_ms": kt.other_ms / steps,
+                     "particle_steps_per_s": n * steps / wall}
+        print(f"[features {name}] {wall * 1e3 / steps:.3f} ms/step (collide "
+              f"{kt.collide_ms / steps:.3f})", file=sys.stderr, flush=True)
+    plain = out["plain"]["ms_per_step"]
+    for v in out.values():
+        v["relative_to_plain"] = v["ms_per_step"] / plain
+    return {"workload": "100^3 cells, 10/cell (10,000,000 particles), FP64, R = 20, "
+                        f"{steps} steps per feature set", "sets": out}
+
+
+def run_reorder_sweep(mpc, torch, synth, steps: int = 200):
+    """Time per step against the reorder interval R (1, 5, 20, 100, never) on
+    the 128^3 box with SRD+a and the thermostat (the paper's reorder-interval
+    experiment, Sec. III.B.3): here R only decides when the logical order is
+    renumbered, so the cost should not depend on it."""
+    out = {}
+    box = dict(synth.config("C1"), L=(128, 128, 128), amc=True, mbs=True)
+    for R in (1, 5, 20, 100, 0):
+        n, wall, kt, obs = run_box(mpc, torch, box, "fp64", R, steps, 10)
+        out[str(R) if R else "never"] = wall * 1e3 / steps
+    print("[reorder sweep] " + ", ".join(f"R={k}: {v:.3f}" for k, v in out.items()) + " ms/step",
+          file=sys.stderr, flush=True)
+    return {"workload": "128^3 cells, 10/cell, FP64, SRD+a + MBS, "
+                        f"{steps} steps per interval", "ms_per_step": out}
+
+
 def cpu_baseline(seconds_hint: float = 15.0):
     """Single-threaded FP64 oracle on a 128^3 sample of the 256^3 workload."""
     import oracle
@@ -229,7 +270,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--forms",
                     default="fp32,split,fp64_sorted_every_step,batched,amc,amc_split,fp64_fixed,"
-                            "walls_slip,walls_couette",
+                            "walls_slip,walls_couette,features,reorder_sweep",
                     help="extra entries besides the FP64 headline (comma list, or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=500)
@@ -386,6 +427,10 @@ def main():
                 forms[form]["collide_traffic_bytes"] = tra["bytes_per_launch"] if tra else None
                 print(f"[{form} C2] {w2 * 1e3 / args.steps:.3f} ms/step collide {c2:.3f} ms",
                       file=sys.stderr)
+            elif form == "features":
+                forms["features"] = run_features(mpc, torch, synth)
+            elif form == "reorder_sweep":
+                forms["reorder_sweep"] = run_reorder_sweep(mpc, torch, synth)
             elif form == "c3":
                 forms["c3"] = run_c3(mpc, torch, synth, args.c3_steps)
             elif form == "c5":
