@@ -41,7 +41,8 @@ class _Params(C.Structure):
                 ("amc", C.c_int32), ("fixed", C.c_int32), ("slip", C.c_int32),
                 ("h", C.c_double), ("alpha", C.c_double),
                 ("kT", C.c_double), ("mass", C.c_double), ("density", C.c_double),
-                ("g", C.c_double * 3), ("seed", C.c_uint64), ("uwall", C.c_double)]
+                ("g", C.c_double * 3), ("seed", C.c_uint64), ("uwall", C.c_double),
+                ("le_u", C.c_double)]
 
 
 @dataclass
@@ -60,6 +61,7 @@ class Params:
     fixed: bool = False
     slip: bool = False
     uwall: float = 0.0
+    le_u: float = 0.0
     g: tuple = field(default_factory=lambda: (0.0, 0.0, 0.0))
 
     def c(self) -> _Params:
@@ -69,6 +71,7 @@ class Params:
         p.fixed = int(self.fixed)
         p.slip = int(self.slip)
         p.uwall = float(self.uwall)
+        p.le_u = float(self.le_u)
         p.h, p.alpha, p.kT, p.mass = self.h, self.alpha, self.kT, self.mass
         p.density = self.density
         p.g[:] = [float(v) for v in self.g]
@@ -127,7 +130,7 @@ def load(path: str):
             "orc_u32_open": (C.c_double, [C.c_uint32]),
             "orc_shift": (None, [P, C.c_uint64, f64p]),
             "orc_ncells": (C.c_int64, [P]),
-            "orc_stream": (C.c_int64, [P, C.c_int64, f64p, f64p]),
+            "orc_stream": (C.c_int64, [P, C.c_uint64, C.c_int64, f64p, f64p]),
             "orc_keys": (C.c_int, [P, C.c_uint64, C.c_int64, f64p, u32p]),
             "orc_sort": (None, [C.c_int64, u32p, C.c_int64, u32p, u32p]),
             "orc_wall_fraction": (C.c_double, [P, C.c_double, C.c_int32]),
@@ -221,11 +224,12 @@ def rotate(alpha: float, n, u) -> np.ndarray:
 
 
 # --- the step, part by part -----------------------------------------------
-def stream(p: Params, x, v):
-    """Eq.(1) with periodic wrap / bounce-back walls.  Returns (x, v, bounces)."""
+def stream(p: Params, x, v, t: int = 0):
+    """Eq.(1) of step t with periodic wrap (Lees-Edwards offset of time
+    (t+1) h) or walls.  Returns (x, v, bounces)."""
     x, v = _state(x, v)
     x, v = x.copy(), v.copy()
-    nb = lib().orc_stream(C.byref(p.c()), x.shape[1], _f64(x), _f64(v))
+    nb = lib().orc_stream(C.byref(p.c()), t, x.shape[1], _f64(x), _f64(v))
     return x, v, int(nb)
 
 
@@ -263,7 +267,8 @@ def collide(p: Params, t: int, v, perm, offset, cells: bool = False, x=None):
     if rc == -3:
         raise ValueError("a fixed-point summand is outside |x| < 2^37")
     if rc != 0:
-        raise ValueError("SRD+a needs positions and is defined for periodic boxes")
+        raise ValueError("SRD+a and Lees-Edwards need positions; SRD+a is defined for "
+                         "periodic boxes, Lees-Edwards for periodic boxes without SRD+a")
     if cells:
         return v, co.reshape(ncell, CELL_STRIDE)
     return v

@@ -108,7 +108,24 @@ static double wrap(double x, double L) {
 /* v <- 2u - v, r <- r_end - 2 (v - u) t_rem.  Slip walls reflect            */
 /* specularly: only v_z and z are mirrored.                                   */
 /* ------------------------------------------------------------------------ */
-int64_t orc_stream(const orc_params* p, int64_t n, double* x, double* v) {
+/* Lees-Edwards shear (Sec. II, boundary conditions: periodic boundaries with
+ * shear flow): at time tau the periodic image above the box (z + L_z) is
+ * displaced by d(tau) = (U tau) mod L_x along x and moves with velocity U.
+ * tau = t_end h, the end of the streaming of step t_end - 1. */
+static double le_offset(const orc_params* p, uint64_t t_end) {
+  double d = p->le_u * ((double)t_end * p->h);
+  return d - (double)p->L[0] * floor(d / (double)p->L[0]);
+}
+
+/* Lees-Edwards frame of a particle in the collision of step t: +1 or -1 if
+ * its shifted cell lies across the lower or upper z face (the cell is formed
+ * with the image on the other side), else 0. */
+static int le_side(const orc_params* p, double z, double sz) {
+  double cz = floor(z + sz);
+  return cz < 0.0 ? 1 : (cz >= (double)p->L[2] ? -1 : 0);
+}
+
+int64_t orc_stream(const orc_params* p, uint64_t t, int64_t n, double* x, double* v) {
   const double h = p->h;
   const double Lx = p->L[0], Ly = p->L[1], Lz = p->L[2];
   int64_t bounces = 0;
@@ -145,6 +162,17 @@ int64_t orc_stream(const orc_params* p, int64_t n, double* x, double* v) {
         ++bounces;
       }
     } else {
+      if (p->le_u != 0.0 && (ze >= Lz || ze < 0.0)) {
+        /* through the sheared face: into the frame of the image it came from */
+        double d = le_offset(p, t + 1);
+        if (ze >= Lz) {
+          xe = xe - d;
+          v[i] = v[i] - p->le_u;
+        } else {
+          xe = xe + d;
+          v[i] = v[i] + p->le_u;
+        }
+      }
       ze = wrap(ze, Lz);
     }
     x[i] = wrap(xe, Lx);
@@ -175,6 +203,14 @@ int orc_keys(const orc_params* p, uint64_t t, int64_t n, const double* x, uint32
         continue;
       }
       c[k] = (int64_t)floor(y);
+    }
+    if (ok && !p->walls && p->le_u != 0.0 && (c[2] < 0 || c[2] >= p->L[2])) {
+      /* Lees-Edwards: a cell across a z face is formed with the image on the
+       * other side, displaced by -/+ d along x */
+      double d = le_offset(p, t + 1);
+      double xi = c[2] >= p->L[2] ? x[i] - d : x[i] + d;
+      int64_t cx = (int64_t)floor(xi + s[0]) % p->L[0];
+      c[0] = cx < 0 ? cx + p->L[0] : cx;
     }
     if (ok) {
       for (int k = 0; k < 2; ++k) {
@@ -484,6 +520,7 @@ static void amc_cell(const orc_params* p, const double s[3], int64_t n, const do
 int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, double* v,
                 const uint32_t* perm, const uint32_t* offset, int64_t ncell, double* cell_out) {
   if (p->amc && (p->walls || !x)) return -2;
+  if (p->le_u != 0.0 && (p->walls || p->amc || !x)) return -2;
   int bad = 0; /* a fixed-point summand out of range */
   const double m = p->mass;
   double* v0 = NULL; /* pre-collision velocities (SRD+a) */
@@ -518,6 +555,18 @@ int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, dou
       }
     }
     int64_t ntot = nf + np;
+    /* Lees-Edwards: the particles of a colliding cell across a z face take the
+     * velocity frame of the image they are mapped to (v_x - U above the upper
+     * face, + U below the lower one) for the collision, and leave it after */
+    const int le = p->le_u != 0.0 && ntot >= 2;
+    if (le) {
+      for (uint32_t j = b; j < e; ++j) {
+        uint32_t i = perm[j];
+        int side = le_side(p, x[2 * n + i], s[2]);
+        if (side < 0) v[i] = v[i] - p->le_u;
+        if (side > 0) v[i] = v[i] + p->le_u;
+      }
+    }
 
     orc_sum Ps[3] = {sum_new(p), sum_new(p), sum_new(p)};
     for (uint32_t j = b; j < e; ++j) {
@@ -611,6 +660,14 @@ int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, dou
         }
       }
     }
+    if (le) {
+      for (uint32_t j = b; j < e; ++j) {
+        uint32_t i = perm[j];
+        int side = le_side(p, x[2 * n + i], s[2]);
+        if (side < 0) v[i] = v[i] + p->le_u;
+        if (side > 0) v[i] = v[i] - p->le_u;
+      }
+    }
     if (co) {
       co[ORC_C_NX] = ax[0];
       co[ORC_C_NY] = ax[1];
@@ -647,7 +704,7 @@ int orc_step(const orc_params* p, uint64_t t, int64_t n, double* x, double* v, i
   uint32_t* key = (uint32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
   uint32_t* perm = (uint32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
   uint32_t* offset = (uint32_t*)malloc(((size_t)ncell + 1) * sizeof(uint32_t));
-  orc_stream(p, n, x, v);
+  orc_stream(p, t, n, x, v);
   int rc = orc_keys(p, t, n, x, key);
   if (rc == 0) {
     orc_sort(n, key, ncell, perm, offset);

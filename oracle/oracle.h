@@ -12,7 +12,8 @@
  *   Sec. II Eq.(2)  SRD rotation about random axis -> orc_collide
  *   Sec. II Eqs.(3)-(4) angular-momentum conserving SRD+a -> orc_collide
  *   Sec. II (Thermostat) MBS scaling, Gamma law    -> orc_collide / orc_gamma
- *   Sec. II (Boundary conditions) bounce-back, phantom particles
+ *   Sec. II (Boundary conditions) bounce-back, phantom particles, moving and
+ *                   slip walls, Lees-Edwards shear of a periodic box
  *   Sec. II (External fields) constant gravity
  *   Sec. III.B.3 (Permanent exchange) reorder by cell -> orc_reorder
  *   Sec. III.C      fixed-point cell sums (optional)  -> orc_collide
@@ -51,6 +52,8 @@ typedef struct {
   uint64_t seed;      /* Philox key                                            */
   double   uwall;     /* no-slip walls: the wall at z = H moves with velocity
                          +uwall along x, the wall at z = 0 with -uwall      */
+  double   le_u;      /* periodic box, Lees-Edwards shear: the image above
+                         (z + L_z) moves with +le_u along x; 0 = plain      */
 } orc_params;
 
 /* Per-cell diagnostics written by orc_collide when cell_out != NULL
@@ -81,7 +84,7 @@ void orc_shift(const orc_params* p, uint64_t t, double s[3]);
 int64_t orc_ncells(const orc_params* p);
 
 /* Eq.(1) + boundary conditions, in place.  Returns the number of bounces. */
-int64_t orc_stream(const orc_params* p, int64_t n, double* x, double* v);
+int64_t orc_stream(const orc_params* p, uint64_t t, int64_t n, double* x, double* v);
 
 /* Cell key of every particle after the shift of step t.  Returns 0, or -1 if
  * a position is not finite / outside the box (key set to 0). */
@@ -112,7 +115,8 @@ void orc_rotate(double alpha, const double n[3], const double u[3], double out[3
 /* Collision of step t on already streamed velocities v, given the sort.
  * x (post-stream positions) is read only with p->amc (it may be NULL
  * otherwise); cell_out (optional) receives ORC_CELL_STRIDE doubles per cell.
- * Returns -2 for amc with walls or without x, -3 (p->fixed) for a summand
+ * Lees-Edwards (p->le_u) also reads x.  Returns -2 for amc with walls or
+ * without x, for le_u with walls, amc or without x, -3 (p->fixed) for a summand
  * outside the fixed-point range |x| < 2^37. */
 int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, double* v,
                 const uint32_t* perm, const uint32_t* offset, int64_t ncell,

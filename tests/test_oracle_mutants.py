@@ -64,6 +64,15 @@ MUTANTS = {
     "amc_mbs_pre_energy": ("if (have_ek && K2 > 0.0) kappa = sqrt((2.0 * Ek) / K2);",
                            "if (have_ek && K2 > 0.0) kappa = sqrt((2.0 * Ek) / K);"),
     "amc_mbs_scaled_twice": ("const double kr = p->amc ? 1.0 : kappa;", "const double kr = kappa;"),
+    "le_offset_time": ("double d = le_offset(p, t + 1);\n        if (ze >= Lz) {",
+                       "double d = le_offset(p, t);\n        if (ze >= Lz) {"),
+    "le_stream_sign": ("          xe = xe - d;", "          xe = xe + d;"),
+    "le_stream_velocity": ("          v[i] = v[i] - p->le_u;\n        } else {",
+                           "          v[i] = v[i] + p->le_u;\n        } else {"),
+    "le_keys_image_sign": ("double xi = c[2] >= p->L[2] ? x[i] - d : x[i] + d;",
+                           "double xi = c[2] >= p->L[2] ? x[i] + d : x[i] - d;"),
+    "le_frame_not_restored": ("if (side < 0) v[i] = v[i] + p->le_u;", "if (side < 0) v[i] = v[i];"),
+    "le_no_collision_frame": ("const int le = p->le_u != 0.0 && ntot >= 2;", "const int le = 0;"),
     "fixed_rounds_terms": ("a->s += (__int128)(x * 0x1p80);", "a->s += (__int128)nearbyint(x * 0x1p80);"),
     "fixed_scale_back": ("(double)a->s * 0x1p-80", "(double)a->s * 0x1p-79"),
     "fixed_range": ("} else if (fabs(x) < 0x1p37) {", "} else if (fabs(x) < 0x1p60) {"),
@@ -83,6 +92,8 @@ FAST_PINS = [
     "test_fixed_sums_exact", "test_fixed_sums_order_independent", "test_fixed_sums_range",
     "test_moving_wall_bounce_is_galilean", "test_slip_walls_reflect_specularly",
     "test_slip_walls_exert_no_tangential_force", "test_couette_profile",
+    "test_lees_edwards_stream", "test_lees_edwards_keys_use_the_image",
+    "test_lees_edwards_momentum_budget", "test_lees_edwards_shear_profile",
 ]
 
 PARAMS = {"test_keys_exact_floor": [{"walls": False}, {"walls": True}],

@@ -849,3 +849,93 @@ def test_couette_profile(orc):
     print(f"Couette: slope {slope:.4f} (2U/H = {2 * U / L[2]:.4f}), intercept {icpt:.4f}, R2 {r2:.4f}")
     assert abs(slope / (2 * U / L[2]) - 1) < 0.1
     assert abs(icpt) < 0.02 and r2 > 0.98
+
+
+# --- Lees-Edwards shear of a periodic box (Sec. II, boundary conditions) ------
+def _le_offset(U, t_end, h, Lx):
+    return (U * t_end * h) % Lx
+
+
+def test_lees_edwards_stream(orc):
+    """A particle through the upper z face re-enters at the bottom displaced by
+    -d along x with v_x - U (it is the image of one below the box); through
+    the lower face +d and + U; d = (U (t+1) h) mod L_x."""
+    L = (8, 6, 6)
+    U, t = 0.9, 13
+    p = orc.Params(L=L, h=0.5, le_u=U)
+    x, v = synth.box_state(L, n=4000, seed=53)
+    v *= 3.0
+    x2, v2, _ = orc.stream(p, x, v, t=t)
+    free, _, _ = orc.stream(orc.Params(L=L, h=0.5), x, v, t=t)
+    zend = x[2] + p.h * v[2]
+    up, down = zend >= L[2], zend < 0
+    assert up.sum() > 100 and down.sum() > 100
+    d = _le_offset(U, t + 1, p.h, L[0])
+    for sel, sgn in ((up, -1.0), (down, 1.0)):
+        ex = (x[0, sel] + p.h * v[0, sel] + sgn * d) % L[0]
+        dd = np.abs(x2[0, sel] - ex)
+        assert np.minimum(dd, L[0] - dd).max() < 1e-12
+        np.testing.assert_allclose(v2[0, sel], v[0, sel] + sgn * U, rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(x2[1:], free[1:])
+    rest = ~(up | down)
+    np.testing.assert_array_equal(x2[:, rest], free[:, rest])
+    np.testing.assert_array_equal(v2[:, rest], v[:, rest])
+
+
+def test_lees_edwards_keys_use_the_image(orc):
+    """A particle whose shifted cell lies across a z face is binned as its image
+    on the other side: the plain periodic keys of (x -/+ d, y, z -/+ L_z)."""
+    L = (8, 6, 6)
+    U, t = 0.7, 21
+    p = orc.Params(L=L, le_u=U, seed=9)
+    plain = orc.Params(L=L, seed=9)
+    x, _ = synth.box_state(L, n=20000, seed=59)
+    s = orc.shift(p, t)
+    d = _le_offset(U, t + 1, p.h, L[0])
+    cz = np.floor(x[2] + s[2])
+    xm = x.copy()
+    top, bot = cz >= L[2], cz < 0
+    assert top.sum() + bot.sum() > 100
+    xm[0, top] = (x[0, top] - d) % L[0]
+    xm[2, top] = x[2, top] - L[2]
+    xm[0, bot] = (x[0, bot] + d) % L[0]
+    xm[2, bot] = x[2, bot] + L[2]
+    np.testing.assert_array_equal(orc.keys(p, t, x), orc.keys(plain, t, xm))
+
+
+def test_lees_edwards_momentum_budget(orc):
+    """Collisions conserve momentum in each cell's frame, so a step changes the
+    total x momentum only through the face crossings: by U (n_down - n_up)."""
+    L = (8, 6, 6)
+    U, t = 0.6, 4
+    p = orc.Params(L=L, le_u=U, mbs=True, seed=15)
+    x, v = synth.box_state(L, seed=61)
+    v *= 2.0
+    zend = x[2] + p.h * v[2]
+    n_up, n_down = int((zend >= L[2]).sum()), int((zend < 0).sum())
+    assert n_up + n_down > 20
+    x2, v2 = orc.step(p, t, x, v)
+    dP = v2[0].sum() - v[0].sum()
+    assert abs(dP - U * (n_down - n_up)) < 1e-11 * x.shape[1]
+
+
+def test_lees_edwards_shear_profile(orc):
+    """Steady Lees-Edwards shear: the averaged v_x(z) is linear with slope
+    U / L_z through the whole box (no walls, so no slip)."""
+    L = (6, 6, 12)
+    U = 0.6
+    p = orc.Params(L=L, le_u=U, mbs=True, seed=21)
+    x, v = synth.box_state(L, seed=63)
+    x, v = orc.run(p, x, v, 400)
+    nb = 12
+    acc = np.zeros(nb)
+    cnt = np.zeros(nb)
+    for t in range(400, 1600, 4):
+        x, v = orc.run(p, x, v, 4, t0=t)
+        b = np.minimum((x[2] / L[2] * nb).astype(int), nb - 1)
+        acc += np.bincount(b, v[0], nb)
+        cnt += np.bincount(b, minlength=nb)
+    z = (np.arange(nb) + 0.5) * L[2] / nb
+    slope, icpt = np.polyfit(z, acc / cnt, 1)
+    print(f"Lees-Edwards: slope {slope:.4f} (U/L_z = {U / L[2]:.4f})")
+    assert abs(slope / (U / L[2]) - 1) < 0.05
