@@ -16,6 +16,7 @@ timed region; 200 steps by default).  The same line carries:
                  conserving collision SRD+a in FP64 and split-FP32, FP64
                  with fixed-point (order-independent) cell sums, the
                  256x256x64 channel with slip walls or moving walls, the
+                 256^3 box under Lees-Edwards shear, the
                  cost of each collision feature on 100^3 and the reorder-
                  interval sweep on 128^3;
   cpu_baseline : the single-threaded CPU oracle on a bounded sample.
@@ -270,7 +271,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--forms",
                     default="fp32,split,fp64_sorted_every_step,batched,amc,amc_split,fp64_fixed,"
-                            "walls_slip,walls_couette,features,reorder_sweep",
+                            "walls_slip,walls_couette,lees_edwards,features,reorder_sweep",
                     help="extra entries besides the FP64 headline (comma list, or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=500)
@@ -390,6 +391,21 @@ def main():
                     "collide_achieved_GBs": n2 * 2 * STATE_BYTES["fp64"] / (c2 * 1e-3) / 1e9,
                     "launch": run_box.last_tiling}
                 print(f"[{form}] N={n2} {w2 * 1e3 / args.steps:.3f} ms/step collide {c2:.3f} ms",
+                      file=sys.stderr)
+            elif form == "lees_edwards":
+                lbox = dict(box, le_u=0.5)
+                n2, w2, k2, o2 = run_box(mpc, torch, lbox, "fp64", R, args.steps, args.warmup)
+                v2 = n2 * args.steps / w2
+                c2 = k2.collide_ms / max(1, k2.collide_launches)
+                forms[form] = {
+                    "workload": f"same 256^3 box and thermostat, FP64, Lees-Edwards shear "
+                                f"(image velocity 0.5), reorder every {R} steps",
+                    "value": v2, "unit": "particle-steps/s",
+                    "ms_per_step": w2 * 1e3 / args.steps,
+                    "collide_ms": c2,
+                    "collide_achieved_GBs": n2 * 2 * STATE_BYTES["fp64"] / (c2 * 1e-3) / 1e9,
+                    "launch": run_box.last_tiling}
+                print(f"[{form} C2] {w2 * 1e3 / args.steps:.3f} ms/step collide {c2:.3f} ms",
                       file=sys.stderr)
             elif form == "fp64_fixed":
                 fbox = dict(box, fixed=True)

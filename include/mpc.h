@@ -125,6 +125,15 @@ typedef struct {
   double   wall_u;        /* no-slip walls (MPC_WALLS_Z without MPC_SLIP): the wall at
                              z = H moves with velocity +wall_u along x and the wall at
                              z = 0 with -wall_u (shear flow); 0 otherwise            */
+  double   le_u;          /* periodic box, Lees-Edwards shear flow (Sec. II, boundary
+                             conditions): the periodic image above the box (z + L[2] a)
+                             moves with +le_u along x and is displaced by
+                             (le_u tau) mod (L[0] a) at time tau = t dt.  A particle
+                             through a z face re-enters shifted by -/+ that offset
+                             with v_x -/+ le_u; a collision cell across a z face is
+                             formed with the image on the other side, in its velocity
+                             frame.  0 = plain periodic.  With MPC_WALLS_Z or MPC_AMC
+                             -> MPC_EINVAL                                          */
 } mpc_params;
 
 /* Observables of one box (FP64, compensated sums over the particles). */

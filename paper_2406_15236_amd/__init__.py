@@ -37,7 +37,7 @@ class Params(C.Structure):
                 ("reorder_every", C.c_int32), ("a", C.c_double), ("density", C.c_double),
                 ("dt", C.c_double), ("alpha", C.c_double), ("kT", C.c_double),
                 ("mass", C.c_double), ("g", C.c_double * 3), ("seed", C.c_uint64),
-                ("wall_u", C.c_double)]
+                ("wall_u", C.c_double), ("le_u", C.c_double)]
 
 
 class Obs(C.Structure):
@@ -137,6 +137,7 @@ def make_params(box: dict, form="fp64", flags: int | None = None, reorder_every:
     p.g[:] = [float(v) for v in box.get("g", (0.0, 0.0, 0.0))]
     p.seed = int(box.get("seed", 1)) & 0xFFFFFFFFFFFFFFFF
     p.wall_u = float(box.get("uwall", 0.0))
+    p.le_u = float(box.get("le_u", 0.0))
     return p
 
 

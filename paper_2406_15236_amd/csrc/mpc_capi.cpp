@@ -64,6 +64,9 @@ int validate(const mpc_params* p, int32_t nbox, std::string* why) {
     if (!isfinite(q.wall_u)) return bad("wall_u must be finite");
     if (q.wall_u != 0.0 && (!(q.flags & MPC_WALLS_Z) || (q.flags & MPC_SLIP)))
       return bad("wall_u needs no-slip walls (MPC_WALLS_Z without MPC_SLIP)");
+    if (!isfinite(q.le_u)) return bad("le_u must be finite");
+    if (q.le_u != 0.0 && (q.flags & (MPC_WALLS_Z | MPC_AMC)))
+      return bad("le_u (Lees-Edwards) needs a periodic box without MPC_AMC");
     if ((q.flags & MPC_AMC) && (q.flags & MPC_WALLS_Z))
       return bad("MPC_AMC is defined for periodic boxes (no MPC_WALLS_Z)");
     if (q.form != p[0].form || q.flags != p[0].flags || q.reorder_every != p[0].reorder_every)
@@ -519,6 +522,9 @@ int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
     B.slip = (B.walls && (q.flags & MPC_SLIP)) ? 1u : 0u;
     B.uw = q.wall_u / q.a;
     B.uwf = (float)B.uw;
+    B.le = (!B.walls && q.le_u != 0.0) ? 1u : 0u;
+    B.leu = q.le_u / q.a;
+    B.leuf = (float)B.leu;
     s->boxes.push_back(B);
     for (uint64_t p0 = 0; p0 < P.box[b].n; p0 += kPartBlock)
       s->pblocks.push_back(PBlock{(uint32_t)b, (uint32_t)(pb + p0)});

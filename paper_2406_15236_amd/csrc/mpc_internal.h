@@ -48,6 +48,9 @@ struct BoxDev {
   float uwf;           // uw as float
   double uw;           // no-slip walls: x velocity of the wall at z = H (cells per
                        // unit time); the wall at z = 0 moves with -uw
+  uint32_t le;         // periodic z with Lees-Edwards shear
+  float leuf;          // leu as float
+  double leu;          // Lees-Edwards: x velocity of the image above the box
 };
 
 struct Tile {          // one collide work item: cells [c0, c0 + nc) of box `box`

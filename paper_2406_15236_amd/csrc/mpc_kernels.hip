@@ -193,9 +193,21 @@ __device__ __forceinline__ float wrap32(float x, float L) {
   return x;
 }
 
-// Eq.(1) in FP64 with periodic x, y and (walls) time-reversed bounce-back in z.
+// Lees-Edwards shear of a periodic box (Sec. II, boundary conditions): at
+// time tau = t_end h the image above the box (z + L_z) is displaced by
+// d = (U tau) mod L_x along x and moves with U.  A particle through a z face
+// re-enters displaced by -/+ d with v_x -/+ U; a collision cell across a z
+// face is formed with the image on the other side, in that image's frame.
+__device__ __forceinline__ double le_offset(BoxRef B, uint64_t t_end) {
+  const double d = B.leu * ((double)t_end * B.h);
+  return d - B.Ld[0] * floor(d / B.Ld[0]);
+}
+
+// Eq.(1) in FP64 with periodic x, y and (walls) time-reversed bounce-back in z;
+// dle: Lees-Edwards offset at the end of this streaming.
 template <bool W>
-__device__ __forceinline__ void stream_f64(double (&x)[3], double (&v)[3], BoxRef B) {
+__device__ __forceinline__ void stream_f64(double (&x)[3], double (&v)[3], BoxRef B,
+                                           double dle) {
   double xe = fma(B.h, v[0], x[0]);
   double ye = fma(B.h, v[1], x[1]);
   double ze = fma(B.h, v[2], x[2]);
@@ -220,6 +232,15 @@ __device__ __forceinline__ void stream_f64(double (&x)[3], double (&v)[3], BoxRe
       v[2] = -v[2];
     }
   } else {
+    if (B.le && (ze >= B.Ld[2] || ze < 0.0)) {
+      if (ze >= B.Ld[2]) {
+        xe = xe - dle;
+        v[0] = v[0] - B.leu;
+      } else {
+        xe = xe + dle;
+        v[0] = v[0] + B.leu;
+      }
+    }
     ze = wrap64(ze, B.Ld[2]);
   }
   x[0] = wrap64(xe, B.Ld[0]);
@@ -228,7 +249,7 @@ __device__ __forceinline__ void stream_f64(double (&x)[3], double (&v)[3], BoxRe
 }
 
 template <bool W>
-__device__ __forceinline__ void stream_f32(float (&x)[3], float (&v)[3], BoxRef B) {
+__device__ __forceinline__ void stream_f32(float (&x)[3], float (&v)[3], BoxRef B, double dle) {
   float xe = fmaf(B.hf, v[0], x[0]);
   float ye = fmaf(B.hf, v[1], x[1]);
   float ze = fmaf(B.hf, v[2], x[2]);
@@ -253,6 +274,15 @@ __device__ __forceinline__ void stream_f32(float (&x)[3], float (&v)[3], BoxRef 
       v[2] = -v[2];
     }
   } else {
+    if (B.le && (ze >= B.Lf[2] || ze < 0.0f)) {
+      if (ze >= B.Lf[2]) {
+        xe = xe - (float)dle;
+        v[0] = v[0] - B.leuf;
+      } else {
+        xe = xe + (float)dle;
+        v[0] = v[0] + B.leuf;
+      }
+    }
     ze = wrap32(ze, B.Lf[2]);
   }
   x[0] = wrap32(xe, B.Lf[0]);
@@ -289,7 +319,7 @@ __device__ __forceinline__ void split_from_double(double xd, int& c, float& o) {
 
 template <bool W>
 __device__ __forceinline__ void stream_split(uint32_t& cell, float (&o)[3], float (&v)[3],
-                                             BoxRef B) {
+                                             BoxRef B, double dle) {
   int c[3];
   split_decode(cell, c);
   int cn[3];
@@ -346,6 +376,14 @@ __device__ __forceinline__ void stream_split(uint32_t& cell, float (&o)[3], floa
       for (int k = 0; k < 3; ++k) split_from_double(xe[k], cn[k], on[k]);
     }
   } else {
+    if (B.le && (cn[2] >= B.L[2] || cn[2] < 0)) {
+      // through a sheared face: x -/+ d in FP64, v_x -/+ U
+      const bool up = cn[2] >= B.L[2];
+      double xd = (double)cn[0] + (double)on[0];
+      xd = wrap64(up ? xd - dle : xd + dle, B.Ld[0]);
+      split_from_double(xd, cn[0], on[0]);
+      v[0] = (float)(up ? (double)v[0] - B.leu : (double)v[0] + B.leu);
+    }
     cn[2] = wrap_cell(cn[2], B.L[2]);
   }
   cn[0] = wrap_cell(cn[0], B.L[0]);
@@ -369,7 +407,7 @@ __device__ __forceinline__ int wrap1(int c, int L) {
 template <bool W>
 __device__ __forceinline__ bool coords_of(const int (&ci)[3], const double (&xf)[3],
                                           const double (&s)[3], BoxRef B, int (&c)[3],
-                                          uint32_t& err) {
+                                          uint32_t& err, double dle) {
   bool ok = true;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -377,6 +415,12 @@ __device__ __forceinline__ bool coords_of(const int (&ci)[3], const double (&xf)
     const bool in = y >= -2.0 && y < B.Ld[k] + 2.0;
     ok = ok && in;
     c[k] = ci[k] + (int)floor(in ? y : 0.0);
+  }
+  if (!W && B.le && (c[2] < 0 || c[2] >= B.L[2])) {
+    // Lees-Edwards: a cell across a z face is formed with the image on the
+    // other side (x -/+ d of the collision time)
+    const double xi = c[2] >= B.L[2] ? xf[0] - dle : xf[0] + dle;
+    c[0] = wrap1(ci[0] + (int)floor(xi + s[0]), B.L[0]);
   }
   c[0] = wrap1(c[0], B.L[0]);
   c[1] = wrap1(c[1], B.L[1]);
@@ -400,9 +444,10 @@ __device__ __forceinline__ uint32_t linear_key(const int (&c)[3], BoxRef B) {
 
 template <bool W>
 __device__ __forceinline__ uint32_t key_of(const int (&ci)[3], const double (&xf)[3],
-                                           const double (&s)[3], BoxRef B, uint32_t& err) {
+                                           const double (&s)[3], BoxRef B, uint32_t& err,
+                                           double dle) {
   int c[3];
-  coords_of<W>(ci, xf, s, B, c, err);
+  coords_of<W>(ci, xf, s, B, c, err, dle);
   return linear_key(c, B);
 }
 
@@ -448,20 +493,26 @@ struct Form<kFormF64> {
     }
   }
   template <bool W>
-  __device__ static void stream(P& p, Vv& v, BoxRef B) { stream_f64<W>(p.x, v.v, B); }
+  __device__ static void stream(P& p, Vv& v, BoxRef B, double dle) { stream_f64<W>(p.x, v.v, B, dle); }
   template <bool W>
   __device__ static uint32_t key(const P& p, const double (&s)[3], BoxRef B,
-                                 uint32_t& err) {
+                                 uint32_t& err, double dle) {
     const int ci[3] = {0, 0, 0};
     const double xf[3] = {p.x[0], p.x[1], p.x[2]};
-    return key_of<W>(ci, xf, s, B, err);
+    return key_of<W>(ci, xf, s, B, err, dle);
   }
   template <bool W>
   __device__ static void coords(const P& p, const double (&s)[3], BoxRef B, int (&c)[3],
-                                uint32_t& err) {
+                                uint32_t& err, double dle) {
     const int ci[3] = {0, 0, 0};
     const double xf[3] = {p.x[0], p.x[1], p.x[2]};
-    coords_of<W>(ci, xf, s, B, c, err);
+    coords_of<W>(ci, xf, s, B, c, err, dle);
+  }
+  // Lees-Edwards side of the collision cell: +1 below the lower z face,
+  // -1 above the upper one, else 0
+  __device__ static int le_side(const P& p, double sz, BoxRef B) {
+    const double cz = floor(p.x[2] + sz);
+    return cz < 0.0 ? 1 : (cz >= B.Ld[2] ? -1 : 0);
   }
 };
 
@@ -502,20 +553,24 @@ struct Form<kFormF32> {
     }
   }
   template <bool W>
-  __device__ static void stream(P& p, Vv& v, BoxRef B) { stream_f32<W>(p.x, v.v, B); }
+  __device__ static void stream(P& p, Vv& v, BoxRef B, double dle) { stream_f32<W>(p.x, v.v, B, dle); }
   template <bool W>
   __device__ static uint32_t key(const P& p, const double (&s)[3], BoxRef B,
-                                 uint32_t& err) {
+                                 uint32_t& err, double dle) {
     const int ci[3] = {0, 0, 0};
     const double xf[3] = {(double)p.x[0], (double)p.x[1], (double)p.x[2]};
-    return key_of<W>(ci, xf, s, B, err);
+    return key_of<W>(ci, xf, s, B, err, dle);
   }
   template <bool W>
   __device__ static void coords(const P& p, const double (&s)[3], BoxRef B, int (&c)[3],
-                                uint32_t& err) {
+                                uint32_t& err, double dle) {
     const int ci[3] = {0, 0, 0};
     const double xf[3] = {(double)p.x[0], (double)p.x[1], (double)p.x[2]};
-    coords_of<W>(ci, xf, s, B, c, err);
+    coords_of<W>(ci, xf, s, B, c, err, dle);
+  }
+  __device__ static int le_side(const P& p, double sz, BoxRef B) {
+    const double cz = floor((double)p.x[2] + sz);
+    return cz < 0.0 ? 1 : (cz >= B.Ld[2] ? -1 : 0);
   }
 };
 
@@ -561,24 +616,30 @@ struct Form<kFormSplit> {
     }
   }
   template <bool W>
-  __device__ static void stream(P& p, Vv& v, BoxRef B) {
-    stream_split<W>(p.cell, p.o, v.v, B);
+  __device__ static void stream(P& p, Vv& v, BoxRef B, double dle) {
+    stream_split<W>(p.cell, p.o, v.v, B, dle);
   }
   template <bool W>
   __device__ static uint32_t key(const P& p, const double (&s)[3], BoxRef B,
-                                 uint32_t& err) {
+                                 uint32_t& err, double dle) {
     int ci[3];
     split_decode(p.cell, ci);
     const double xf[3] = {(double)p.o[0], (double)p.o[1], (double)p.o[2]};
-    return key_of<W>(ci, xf, s, B, err);
+    return key_of<W>(ci, xf, s, B, err, dle);
   }
   template <bool W>
   __device__ static void coords(const P& p, const double (&s)[3], BoxRef B, int (&c)[3],
-                                uint32_t& err) {
+                                uint32_t& err, double dle) {
     int ci[3];
     split_decode(p.cell, ci);
     const double xf[3] = {(double)p.o[0], (double)p.o[1], (double)p.o[2]};
-    coords_of<W>(ci, xf, s, B, c, err);
+    coords_of<W>(ci, xf, s, B, c, err, dle);
+  }
+  __device__ static int le_side(const P& p, double sz, BoxRef B) {
+    int ci[3];
+    split_decode(p.cell, ci);
+    const int cz = ci[2] + (int)floor((double)p.o[2] + sz);
+    return cz < 0 ? 1 : (cz >= B.L[2] ? -1 : 0);
   }
 };
 
@@ -653,8 +714,9 @@ __global__ __launch_bounds__(kThreads) void k_key_hist(Dev d) {
       typename Fm::P p;
       typename Fm::Vv v;
       Fm::load(S, i, p, v);
-      Fm::template stream<W>(p, v, B);
-      key = B.cbase + Fm::template key<W>(p, s, B, err);
+      const double dle = W ? 0.0 : le_offset(B, t + 1);
+      Fm::template stream<W>(p, v, B, dle);
+      key = B.cbase + Fm::template key<W>(p, s, B, err, dle);
       d.key[i] = key;
     }
     const uint32_t rk = wave_hist_rank(d.hist, key, i < pend);
@@ -1480,7 +1542,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   __shared__ Xs s_x[3][kTileCap];        // streamed positions (offsets), canonical order
   __shared__ uint32_t s_c[Fm::kHasCell ? kTileCap : 1];
   __shared__ typename CellRec<F, A>::T s_cell[kTileMaxCells];
-  __shared__ double s_sh[6];
+  __shared__ double s_sh[8];  // shifts of t and t + 1; Lees-Edwards offsets of t + 1, t + 2
   // next-step window of the tile: cells x0-1 .. x0+nc of the rows (y0 +- 1,
   // z0 +- 1), plus one entry for particles that leave it; per pass: counts,
   // then their exclusive prefix (the output order of the pass)
@@ -1548,6 +1610,8 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
       s_sh[3] = s1[0];
       s_sh[4] = s1[1];
       s_sh[5] = s1[2];
+      s_sh[6] = W ? 0.0 : le_offset(B, t + 1);
+      s_sh[7] = W ? 0.0 : le_offset(B, t + 2);
     }
     cached_box = T.box;
     const uint32_t lkey0 = T.c0 - B.cbase;
@@ -1606,12 +1670,12 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             typename Fm::P p;
             typename Fm::Vv v;
             Fm::load(in, i, p, v);
-            Fm::template stream<W>(p, v, B);
+            Fm::template stream<W>(p, v, B, s_sh[6]);
             const uint32_t j = base + q;
             Fm::store(out, j, p, v);
             if (track) out.id[j] = renumber ? j : in.id[i];
-            Fm::template stream<W>(p, v, B);
-            kn = B.cbase + Fm::template key<W>(p, snx, B, err);
+            Fm::template stream<W>(p, v, B, s_sh[7]);
+            kn = B.cbase + Fm::template key<W>(p, snx, B, err, s_sh[7]);
             d.key[j] = kn;
           }
           const uint32_t rk = wave_hist_rank(d.hist, kn, live);
@@ -1687,7 +1751,13 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             const uint32_t b = s_off[c] - base, e = s_off[c + 1] - base;
             const uint32_t id = track ? s_rk[q] : i;
             const uint32_t qc = b + rank_in_segment(track ? s_rk : s_idx, b, e, id);
-            Fm::template stream<W>(p[k], v[k], B);
+            Fm::template stream<W>(p[k], v[k], B, s_sh[6]);
+            if (!W && B.le && e - b >= 2u) {
+              // a colliding cell across a z face: its image's velocity frame
+              const int side = Fm::le_side(p[k], s_sh[2], B);
+              if (side < 0) v[k].v[0] = (Vs)((double)v[k].v[0] - B.leu);
+              if (side > 0) v[k].v[0] = (Vs)((double)v[k].v[0] + B.leu);
+            }
             Fm::to_lds(p[k], s_x[0], s_x[1], s_x[2], s_c, qc);
             s_v[0][qc] = v[k].v[0];
             s_v[1][qc] = v[k].v[1];
@@ -1758,6 +1828,11 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
                 v.v[1] = (float)((double)v.v[1] + (C.om[2] * r[0] - C.om[0] * r[2]));
                 v.v[2] = (float)((double)v.v[2] + (C.om[0] * r[1] - C.om[1] * r[0]));
               }
+              if (!W && B.le) {  // leave the Lees-Edwards image frame
+                const int side = Fm::le_side(p, s_sh[2], B);
+                if (side < 0) v.v[0] = (float)((double)v.v[0] + B.leu);
+                if (side > 0) v.v[0] = (float)((double)v.v[0] - B.leu);
+              }
             }
             if (B.grav) {
 #pragma unroll
@@ -1780,6 +1855,11 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
                 w[1] = w[1] + (C.om[2] * rr[0] - C.om[0] * rr[2]);
                 w[2] = w[2] + (C.om[0] * rr[1] - C.om[1] * rr[0]);
               }
+              if (!W && B.le) {  // leave the Lees-Edwards image frame
+                const int side = Fm::le_side(p, s_sh[2], B);
+                if (side < 0) w[0] = w[0] + B.leu;
+                if (side > 0) w[0] = w[0] - B.leu;
+              }
             }
             if (B.grav) {
 #pragma unroll
@@ -1792,9 +1872,9 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
           s_v[0][q] = v.v[0];
           s_v[1][q] = v.v[1];
           s_v[2][q] = v.v[2];
-          Fm::template stream<W>(p, v, B);
+          Fm::template stream<W>(p, v, B, s_sh[7]);
           int c[3];
-          Fm::template coords<W>(p, snext, B, c, err);
+          Fm::template coords<W>(p, snext, B, c, err, s_sh[7]);
           const uint32_t kn = B.cbase + linear_key(c, B);
           int r, dx;
           uint32_t e = (uint32_t)(9 * WX);  // outside the window: counted in D2

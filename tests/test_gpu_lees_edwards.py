@@ -1,0 +1,165 @@
+"""GPU tests of the Lees-Edwards shear of a periodic box (Sec. II, boundary
+conditions; mpc_params.le_u).
+
+  * One step against the oracle: FP64 positions and binning bit-identical,
+    velocities e <= 1e-12 (with the thermostat, fixed-point sums, gravity and
+    several reorder intervals); FP32 and split forms with the usual bars.
+  * Momentum budget on the GPU: a step changes the total x momentum only by
+    U (n_down - n_up), the face crossings.
+  * The steady shear profile: v_x(z) linear with slope U / L_z.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import synth
+
+pytestmark = pytest.mark.gpu
+
+DEG = math.pi / 180.0
+
+
+@pytest.fixture(scope="module")
+def mpc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_15236_amd as m
+    m.lib()
+    return m
+
+
+def box_of(L, U, seed=1, mbs=True, fixed=False, g=(0.0, 0.0, 0.0), **kw):
+    b = dict(L=tuple(L), h=0.1, alpha=130.0 * DEG, kT=1.0, mass=1.0, density=10.0,
+             seed=seed, mbs=mbs, walls=False, fixed=fixed, le_u=U, g=tuple(g))
+    b.update(kw)
+    return b
+
+
+def oparams(box):
+    return orc.Params(L=box["L"], h=box["h"], alpha=box["alpha"], kT=box["kT"],
+                      mass=box["mass"], density=box["density"], seed=box["seed"],
+                      mbs=box["mbs"], fixed=box["fixed"], le_u=box["le_u"], g=box["g"])
+
+
+def rel_err(vg, vo, box):
+    floor = math.sqrt(box["kT"] / box["mass"])
+    return np.linalg.norm(vg - vo, axis=0) / np.maximum(np.linalg.norm(vo, axis=0), floor)
+
+
+LE_CASES = [
+    # L, U, mbs, fixed, gravity, R, t0
+    ((16, 16, 16), 0.5, True, False, (0, 0, 0), 0, 0),
+    ((13, 9, 11), 0.8, False, False, (0, 0, 0), 1, 3),
+    ((12, 10, 8), 0.3, True, True, (1e-3, 0, 0), 3, 2),
+    ((7, 33, 5), 1.7, True, False, (0, 0, 0), 0, 123456),
+]
+
+
+@pytest.mark.parametrize("L,U,mbs,fixed,g,R,t0", LE_CASES)
+def test_lees_edwards_fp64_one_step(mpc, L, U, mbs, fixed, g, R, t0):
+    box = box_of(L, U, seed=5 + t0 % 97, mbs=mbs, fixed=fixed, g=g)
+    x, v = synth.box_state(L, seed=37 + t0 % 89)
+    v *= 2.0  # more face crossings
+    print(f"case le fp64 L={L} U={U} mbs={mbs} fixed={fixed} R={R} t0={t0}", flush=True)
+    with mpc.Sim(box, form="fp64", reorder_every=R) as sim:
+        sim.set_state(x, v)
+        sim.set_step(t0)
+        sim.step(1)
+        xg, vg = sim.get_state()
+        kg, pg, og = sim.get_binning()
+    sorted_out = R > 0 and (t0 + 1) % R == 0
+    xo, vo, ko, po, oo = orc.step(oparams(box), t0, x, v, reorder=sorted_out, binning=True)
+    np.testing.assert_array_equal(kg, ko)
+    np.testing.assert_array_equal(pg, po)
+    np.testing.assert_array_equal(og, oo)
+    np.testing.assert_array_equal(xg, xo)
+    e = rel_err(vg, vo, box)
+    print(f"le fp64: max e = {e.max():.3e}")
+    assert e.max() <= 1e-12
+
+
+@pytest.mark.parametrize("form", ["fp32", "split"])
+def test_lees_edwards_reduced_precision_one_step(mpc, form):
+    L = (16, 12, 10)
+    U = 0.6
+    box = box_of(L, U, seed=9)
+    x, v = synth.box_state(L, seed=27)
+    v *= 2.0
+    t0 = 4
+    with mpc.Sim(box, form=form) as sim:
+        sim.set_state(x, v)
+        x0, v0 = sim.get_state()
+        sim.set_step(t0)
+        sim.step(1)
+        x1, v1 = sim.get_state()
+        kg, pg, og = sim.get_binning()
+    p = oparams(box)
+    xs, vs, _ = orc.stream(p, x0, v0, t=t0)
+    dx = np.abs(x1 - xs)
+    for k in range(3):
+        dx[k] = np.minimum(dx[k], L[k] - dx[k])
+    print(f"le {form}: max stream error {dx.max():.3e} cells")
+    assert dx.max() < 2e-5
+    ko = orc.keys(p, t0, x1)
+    np.testing.assert_array_equal(kg, ko)
+    po, oo = orc.sort(ko, p.ncells)
+    np.testing.assert_array_equal(og, oo)
+    vo = orc.collide(p, t0, vs, po, oo, x=x1)
+    e = rel_err(v1, vo, box)
+    print(f"le {form}: max e = {e.max():.3e}")
+    assert e.max() <= 2e-6
+
+
+def test_lees_edwards_momentum_budget_gpu(mpc):
+    L = (32, 32, 16)
+    U, t0 = 0.7, 5
+    box = box_of(L, U, seed=4)
+    x, v = synth.box_state(L, seed=43)
+    v *= 2.0
+    zend = x[2] + 0.1 * v[2]
+    n_up, n_down = int((zend >= L[2]).sum()), int((zend < 0).sum())
+    with mpc.Sim(box, form="fp64") as sim:
+        sim.set_state(x, v)
+        sim.set_step(t0)
+        p0 = sim.observables()["P"]
+        sim.step(1)
+        p1 = sim.observables()["P"]
+    print(f"le budget: dP_x = {p1[0] - p0[0]:.9f}, U (n_down - n_up) = {U * (n_down - n_up):.9f}")
+    assert abs((p1[0] - p0[0]) - U * (n_down - n_up)) < 1e-10 * x.shape[1]
+
+
+def test_lees_edwards_shear_profile_gpu(mpc):
+    L = (32, 32, 24)
+    U = 0.6
+    box = box_of(L, U, seed=6)
+    nb = 24
+    acc = np.zeros(nb)
+    cnt = np.zeros(nb)
+    with mpc.Sim(box, form="fp64") as sim:
+        sim.init_state(3)
+        sim.step(1500)
+        for _ in range(60):
+            sim.step(25)
+            x, v = sim.get_state()
+            b = np.minimum((x[2] / L[2] * nb).astype(int), nb - 1)
+            acc += np.bincount(b, v[0], nb)
+            cnt += np.bincount(b, minlength=nb)
+    z = (np.arange(nb) + 0.5) * L[2] / nb
+    prof = acc / cnt
+    slope, icpt = np.polyfit(z, prof, 1)
+    resid = prof - (slope * z + icpt)
+    r2 = 1 - (resid ** 2).sum() / ((prof - prof.mean()) ** 2).sum()
+    print(f"Lees-Edwards GPU: slope/theory {slope / (U / L[2]):.4f}, R2 {r2:.5f}")
+    assert abs(slope / (U / L[2]) - 1) < 0.03 and r2 > 0.995
+
+
+def test_lees_edwards_flag_validation(mpc):
+    with pytest.raises(mpc.MPCError) as e:
+        mpc.Sim(box_of((8, 8, 8), 0.3, walls=True))
+    assert e.value.code == mpc.EINVAL
+    with pytest.raises(mpc.MPCError) as e:
+        mpc.Sim(box_of((8, 8, 8), 0.3, amc=True))
+    assert e.value.code == mpc.EINVAL
