@@ -523,6 +523,7 @@ int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
     B.uw = q.wall_u / q.a;
     B.uwf = (float)B.uw;
     B.le = (!B.walls && q.le_u != 0.0) ? 1u : 0u;
+    if (B.le) s->L.le = 1;
     B.leu = q.le_u / q.a;
     B.leuf = (float)B.leu;
     s->boxes.push_back(B);

@@ -122,6 +122,7 @@ struct Launch {
   int round_phantoms;      // split form: phantom velocities rounded to FP32
   int walls, mbs, amc;     // feature flags (identical for all boxes)
   int fixed;               // fixed-point cell sums
+  int le;                  // some box has Lees-Edwards shear
   uint32_t nbox;
   uint64_t ntot, ctot;     // particles, cells over all boxes
   uint32_t ntiles, npblocks, nscan;

@@ -207,7 +207,7 @@ __device__ __forceinline__ double le_offset(BoxRef B, uint64_t t_end) {
 // dle: Lees-Edwards offset at the end of this streaming.
 template <bool W>
 __device__ __forceinline__ void stream_f64(double (&x)[3], double (&v)[3], BoxRef B,
-                                           double dle) {
+                                           double dle, bool le) {
   double xe = fma(B.h, v[0], x[0]);
   double ye = fma(B.h, v[1], x[1]);
   double ze = fma(B.h, v[2], x[2]);
@@ -232,7 +232,7 @@ __device__ __forceinline__ void stream_f64(double (&x)[3], double (&v)[3], BoxRe
       v[2] = -v[2];
     }
   } else {
-    if (B.le && (ze >= B.Ld[2] || ze < 0.0)) {
+    if (le && (ze >= B.Ld[2] || ze < 0.0)) {
       if (ze >= B.Ld[2]) {
         xe = xe - dle;
         v[0] = v[0] - B.leu;
@@ -249,7 +249,8 @@ __device__ __forceinline__ void stream_f64(double (&x)[3], double (&v)[3], BoxRe
 }
 
 template <bool W>
-__device__ __forceinline__ void stream_f32(float (&x)[3], float (&v)[3], BoxRef B, double dle) {
+__device__ __forceinline__ void stream_f32(float (&x)[3], float (&v)[3], BoxRef B, double dle,
+                                           bool le) {
   float xe = fmaf(B.hf, v[0], x[0]);
   float ye = fmaf(B.hf, v[1], x[1]);
   float ze = fmaf(B.hf, v[2], x[2]);
@@ -274,7 +275,7 @@ __device__ __forceinline__ void stream_f32(float (&x)[3], float (&v)[3], BoxRef 
       v[2] = -v[2];
     }
   } else {
-    if (B.le && (ze >= B.Lf[2] || ze < 0.0f)) {
+    if (le && (ze >= B.Lf[2] || ze < 0.0f)) {
       if (ze >= B.Lf[2]) {
         xe = xe - (float)dle;
         v[0] = v[0] - B.leuf;
@@ -319,7 +320,7 @@ __device__ __forceinline__ void split_from_double(double xd, int& c, float& o) {
 
 template <bool W>
 __device__ __forceinline__ void stream_split(uint32_t& cell, float (&o)[3], float (&v)[3],
-                                             BoxRef B, double dle) {
+                                             BoxRef B, double dle, bool le) {
   int c[3];
   split_decode(cell, c);
   int cn[3];
@@ -376,7 +377,7 @@ __device__ __forceinline__ void stream_split(uint32_t& cell, float (&o)[3], floa
       for (int k = 0; k < 3; ++k) split_from_double(xe[k], cn[k], on[k]);
     }
   } else {
-    if (B.le && (cn[2] >= B.L[2] || cn[2] < 0)) {
+    if (le && (cn[2] >= B.L[2] || cn[2] < 0)) {
       // through a sheared face: x -/+ d in FP64, v_x -/+ U
       const bool up = cn[2] >= B.L[2];
       double xd = (double)cn[0] + (double)on[0];
@@ -407,7 +408,7 @@ __device__ __forceinline__ int wrap1(int c, int L) {
 template <bool W>
 __device__ __forceinline__ bool coords_of(const int (&ci)[3], const double (&xf)[3],
                                           const double (&s)[3], BoxRef B, int (&c)[3],
-                                          uint32_t& err, double dle) {
+                                          uint32_t& err, double dle, bool le) {
   bool ok = true;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -416,7 +417,7 @@ __device__ __forceinline__ bool coords_of(const int (&ci)[3], const double (&xf)
     ok = ok && in;
     c[k] = ci[k] + (int)floor(in ? y : 0.0);
   }
-  if (!W && B.le && (c[2] < 0 || c[2] >= B.L[2])) {
+  if (!W && le && (c[2] < 0 || c[2] >= B.L[2])) {
     // Lees-Edwards: a cell across a z face is formed with the image on the
     // other side (x -/+ d of the collision time)
     const double xi = c[2] >= B.L[2] ? xf[0] - dle : xf[0] + dle;
@@ -445,9 +446,9 @@ __device__ __forceinline__ uint32_t linear_key(const int (&c)[3], BoxRef B) {
 template <bool W>
 __device__ __forceinline__ uint32_t key_of(const int (&ci)[3], const double (&xf)[3],
                                            const double (&s)[3], BoxRef B, uint32_t& err,
-                                           double dle) {
+                                           double dle, bool le) {
   int c[3];
-  coords_of<W>(ci, xf, s, B, c, err, dle);
+  coords_of<W>(ci, xf, s, B, c, err, dle, le);
   return linear_key(c, B);
 }
 
@@ -493,20 +494,22 @@ struct Form<kFormF64> {
     }
   }
   template <bool W>
-  __device__ static void stream(P& p, Vv& v, BoxRef B, double dle) { stream_f64<W>(p.x, v.v, B, dle); }
+  __device__ static void stream(P& p, Vv& v, BoxRef B, double dle, bool le) {
+    stream_f64<W>(p.x, v.v, B, dle, le);
+  }
   template <bool W>
   __device__ static uint32_t key(const P& p, const double (&s)[3], BoxRef B,
-                                 uint32_t& err, double dle) {
+                                 uint32_t& err, double dle, bool le) {
     const int ci[3] = {0, 0, 0};
     const double xf[3] = {p.x[0], p.x[1], p.x[2]};
-    return key_of<W>(ci, xf, s, B, err, dle);
+    return key_of<W>(ci, xf, s, B, err, dle, le);
   }
   template <bool W>
   __device__ static void coords(const P& p, const double (&s)[3], BoxRef B, int (&c)[3],
-                                uint32_t& err, double dle) {
+                                uint32_t& err, double dle, bool le) {
     const int ci[3] = {0, 0, 0};
     const double xf[3] = {p.x[0], p.x[1], p.x[2]};
-    coords_of<W>(ci, xf, s, B, c, err, dle);
+    coords_of<W>(ci, xf, s, B, c, err, dle, le);
   }
   // Lees-Edwards side of the collision cell: +1 below the lower z face,
   // -1 above the upper one, else 0
@@ -553,20 +556,22 @@ struct Form<kFormF32> {
     }
   }
   template <bool W>
-  __device__ static void stream(P& p, Vv& v, BoxRef B, double dle) { stream_f32<W>(p.x, v.v, B, dle); }
+  __device__ static void stream(P& p, Vv& v, BoxRef B, double dle, bool le) {
+    stream_f32<W>(p.x, v.v, B, dle, le);
+  }
   template <bool W>
   __device__ static uint32_t key(const P& p, const double (&s)[3], BoxRef B,
-                                 uint32_t& err, double dle) {
+                                 uint32_t& err, double dle, bool le) {
     const int ci[3] = {0, 0, 0};
     const double xf[3] = {(double)p.x[0], (double)p.x[1], (double)p.x[2]};
-    return key_of<W>(ci, xf, s, B, err, dle);
+    return key_of<W>(ci, xf, s, B, err, dle, le);
   }
   template <bool W>
   __device__ static void coords(const P& p, const double (&s)[3], BoxRef B, int (&c)[3],
-                                uint32_t& err, double dle) {
+                                uint32_t& err, double dle, bool le) {
     const int ci[3] = {0, 0, 0};
     const double xf[3] = {(double)p.x[0], (double)p.x[1], (double)p.x[2]};
-    coords_of<W>(ci, xf, s, B, c, err, dle);
+    coords_of<W>(ci, xf, s, B, c, err, dle, le);
   }
   __device__ static int le_side(const P& p, double sz, BoxRef B) {
     const double cz = floor((double)p.x[2] + sz);
@@ -616,24 +621,24 @@ struct Form<kFormSplit> {
     }
   }
   template <bool W>
-  __device__ static void stream(P& p, Vv& v, BoxRef B, double dle) {
-    stream_split<W>(p.cell, p.o, v.v, B, dle);
+  __device__ static void stream(P& p, Vv& v, BoxRef B, double dle, bool le) {
+    stream_split<W>(p.cell, p.o, v.v, B, dle, le);
   }
   template <bool W>
   __device__ static uint32_t key(const P& p, const double (&s)[3], BoxRef B,
-                                 uint32_t& err, double dle) {
+                                 uint32_t& err, double dle, bool le) {
     int ci[3];
     split_decode(p.cell, ci);
     const double xf[3] = {(double)p.o[0], (double)p.o[1], (double)p.o[2]};
-    return key_of<W>(ci, xf, s, B, err, dle);
+    return key_of<W>(ci, xf, s, B, err, dle, le);
   }
   template <bool W>
   __device__ static void coords(const P& p, const double (&s)[3], BoxRef B, int (&c)[3],
-                                uint32_t& err, double dle) {
+                                uint32_t& err, double dle, bool le) {
     int ci[3];
     split_decode(p.cell, ci);
     const double xf[3] = {(double)p.o[0], (double)p.o[1], (double)p.o[2]};
-    coords_of<W>(ci, xf, s, B, c, err, dle);
+    coords_of<W>(ci, xf, s, B, c, err, dle, le);
   }
   __device__ static int le_side(const P& p, double sz, BoxRef B) {
     int ci[3];
@@ -715,8 +720,8 @@ __global__ __launch_bounds__(kThreads) void k_key_hist(Dev d) {
       typename Fm::Vv v;
       Fm::load(S, i, p, v);
       const double dle = W ? 0.0 : le_offset(B, t + 1);
-      Fm::template stream<W>(p, v, B, dle);
-      key = B.cbase + Fm::template key<W>(p, s, B, err, dle);
+      Fm::template stream<W>(p, v, B, dle, !W && B.le);
+      key = B.cbase + Fm::template key<W>(p, s, B, err, dle, !W && B.le);
       d.key[i] = key;
     }
     const uint32_t rk = wave_hist_rank(d.hist, key, i < pend);
@@ -1522,7 +1527,7 @@ struct TileWalk {
   }
 };
 
-template <int F, bool W, bool M, bool A, bool X>
+template <int F, bool W, bool M, bool A, bool X, bool E>
 __global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu((W || A || X) ? 2 : 3)))
 void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   using Fm = Form<F>;
@@ -1610,8 +1615,8 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
       s_sh[3] = s1[0];
       s_sh[4] = s1[1];
       s_sh[5] = s1[2];
-      s_sh[6] = W ? 0.0 : le_offset(B, t + 1);
-      s_sh[7] = W ? 0.0 : le_offset(B, t + 2);
+      s_sh[6] = E ? le_offset(B, t + 1) : 0.0;
+      s_sh[7] = E ? le_offset(B, t + 2) : 0.0;
     }
     cached_box = T.box;
     const uint32_t lkey0 = T.c0 - B.cbase;
@@ -1670,12 +1675,12 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             typename Fm::P p;
             typename Fm::Vv v;
             Fm::load(in, i, p, v);
-            Fm::template stream<W>(p, v, B, s_sh[6]);
+            Fm::template stream<W>(p, v, B, s_sh[6], E && B.le);
             const uint32_t j = base + q;
             Fm::store(out, j, p, v);
             if (track) out.id[j] = renumber ? j : in.id[i];
-            Fm::template stream<W>(p, v, B, s_sh[7]);
-            kn = B.cbase + Fm::template key<W>(p, snx, B, err, s_sh[7]);
+            Fm::template stream<W>(p, v, B, s_sh[7], E && B.le);
+            kn = B.cbase + Fm::template key<W>(p, snx, B, err, s_sh[7], E && B.le);
             d.key[j] = kn;
           }
           const uint32_t rk = wave_hist_rank(d.hist, kn, live);
@@ -1751,8 +1756,8 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             const uint32_t b = s_off[c] - base, e = s_off[c + 1] - base;
             const uint32_t id = track ? s_rk[q] : i;
             const uint32_t qc = b + rank_in_segment(track ? s_rk : s_idx, b, e, id);
-            Fm::template stream<W>(p[k], v[k], B, s_sh[6]);
-            if (!W && B.le && e - b >= 2u) {
+            Fm::template stream<W>(p[k], v[k], B, s_sh[6], E && B.le);
+            if (E && B.le && e - b >= 2u) {
               // a colliding cell across a z face: its image's velocity frame
               const int side = Fm::le_side(p[k], s_sh[2], B);
               if (side < 0) v[k].v[0] = (Vs)((double)v[k].v[0] - B.leu);
@@ -1828,7 +1833,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
                 v.v[1] = (float)((double)v.v[1] + (C.om[2] * r[0] - C.om[0] * r[2]));
                 v.v[2] = (float)((double)v.v[2] + (C.om[0] * r[1] - C.om[1] * r[0]));
               }
-              if (!W && B.le) {  // leave the Lees-Edwards image frame
+              if (E && B.le) {  // leave the Lees-Edwards image frame
                 const int side = Fm::le_side(p, s_sh[2], B);
                 if (side < 0) v.v[0] = (float)((double)v.v[0] + B.leu);
                 if (side > 0) v.v[0] = (float)((double)v.v[0] - B.leu);
@@ -1855,7 +1860,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
                 w[1] = w[1] + (C.om[2] * rr[0] - C.om[0] * rr[2]);
                 w[2] = w[2] + (C.om[0] * rr[1] - C.om[1] * rr[0]);
               }
-              if (!W && B.le) {  // leave the Lees-Edwards image frame
+              if (E && B.le) {  // leave the Lees-Edwards image frame
                 const int side = Fm::le_side(p, s_sh[2], B);
                 if (side < 0) w[0] = w[0] + B.leu;
                 if (side > 0) w[0] = w[0] - B.leu;
@@ -1872,9 +1877,9 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
           s_v[0][q] = v.v[0];
           s_v[1][q] = v.v[1];
           s_v[2][q] = v.v[2];
-          Fm::template stream<W>(p, v, B, s_sh[7]);
+          Fm::template stream<W>(p, v, B, s_sh[7], E && B.le);
           int c[3];
-          Fm::template coords<W>(p, snext, B, c, err, s_sh[7]);
+          Fm::template coords<W>(p, snext, B, c, err, s_sh[7], E && B.le);
           const uint32_t kn = B.cbase + linear_key(c, B);
           int r, dx;
           uint32_t e = (uint32_t)(9 * WX);  // outside the window: counted in D2
@@ -1995,27 +2000,37 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
 // Runtime flags (form, walls, thermostat, SRD+a, fixed-point sums) -> the
 // k_collide instantiation.  SRD+a next to walls is not built.
 struct CollideLaunchOp {
-  template <int F, bool W, bool M, bool A, bool X>
+  template <int F, bool W, bool M, bool A, bool X, bool E>
   static hipError_t run(const Dev& d, const Launch& l, int*) {
-    hipLaunchKernelGGL((k_collide<F, W, M, A, X>), dim3(l.collide_grid), dim3(kCollideThreads), 0,
-                       l.stream, d, (uint32_t)l.ntiles, l.xcd_remap);
+    hipLaunchKernelGGL((k_collide<F, W, M, A, X, E>), dim3(l.collide_grid),
+                       dim3(kCollideThreads), 0, l.stream, d, (uint32_t)l.ntiles, l.xcd_remap);
     return hipGetLastError();
   }
 };
 struct CollideOccOp {
-  template <int F, bool W, bool M, bool A, bool X>
+  template <int F, bool W, bool M, bool A, bool X, bool E>
   static hipError_t run(const Dev&, const Launch&, int* n) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_collide<F, W, M, A, X>,
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_collide<F, W, M, A, X, E>,
                                                         kCollideThreads, 0);
   }
 };
+// Lees-Edwards (E) is built for periodic boxes without SRD+a only.
+template <class Op, int F, bool W, bool M, bool A, bool X>
+static hipError_t collide_pick_e(const Dev& d, const Launch& l, int* n) {
+  if constexpr (W || A) {
+    return l.le ? hipErrorInvalidValue : Op::template run<F, W, M, A, X, false>(d, l, n);
+  } else {
+    return l.le ? Op::template run<F, W, M, A, X, true>(d, l, n)
+                : Op::template run<F, W, M, A, X, false>(d, l, n);
+  }
+}
 template <class Op, int F, bool W, bool M, bool A>
 static hipError_t collide_pick_x(const Dev& d, const Launch& l, int* n) {
   if constexpr (A && W) {
     return hipErrorInvalidValue;
   } else {
-    return l.fixed ? Op::template run<F, W, M, A, true>(d, l, n)
-                   : Op::template run<F, W, M, A, false>(d, l, n);
+    return l.fixed ? collide_pick_e<Op, F, W, M, A, true>(d, l, n)
+                   : collide_pick_e<Op, F, W, M, A, false>(d, l, n);
   }
 }
 template <class Op, int F, bool W, bool M>
