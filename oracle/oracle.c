@@ -438,7 +438,7 @@ static double sum_val(const orc_sum* a) { return a->fixed ? (double)a->s * 0x1p-
  * singular I; the change of angular momentum then lies in I's range and the
  * pseudo-inverse, omega = dL / (m |r_1 - r_2|^2 / 2), is used; three or more
  * particles use I^-1 (Cramer's rule), and omega = 0 if det I = 0.  Periodic
- * boxes only (phantom particles carry no positions).  With the thermostat, the
+ * boxes or slip walls only (phantom particles carry no positions).  With the thermostat, the
  * scaling is applied to the corrected relative velocities (see orc_collide). */
 static void amc_cell(const orc_params* p, const double s[3], int64_t n, const double* x,
                      const double* v0, double* v, const uint32_t* perm, uint32_t b, uint32_t e,
@@ -519,7 +519,7 @@ static void amc_cell(const orc_params* p, const double s[3], int64_t n, const do
 
 int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, double* v,
                 const uint32_t* perm, const uint32_t* offset, int64_t ncell, double* cell_out) {
-  if (p->amc && (p->walls || !x)) return -2;
+  if (p->amc && ((p->walls && !p->slip) || !x)) return -2;
   if (p->le_u != 0.0 && (p->walls || p->amc || !x)) return -2;
   int bad = 0; /* a fixed-point summand out of range */
   const double m = p->mass;

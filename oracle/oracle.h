@@ -37,8 +37,8 @@ typedef struct {
   int32_t  walls;     /* 1: no-slip walls at z = 0 and z = H (bounce-back)     */
   int32_t  mbs;       /* 1: Maxwell-Boltzmann-scaling thermostat              */
   int32_t  amc;       /* 1: cell angular momentum conserved (SRD+a, Eqs. 3-4);
-                         periodic boxes only; with mbs the scaling follows the
-                         correction                                            */
+                         periodic boxes or slip walls (no phantoms); with mbs
+                         the scaling follows the correction                   */
   int32_t  fixed;     /* 1: cell sums of fluid terms in fixed point (Sec.
                          III.C, reproducibility): independent of the order  */
   int32_t  slip;      /* with walls, 1: slip walls (specular reflection, no
@@ -115,7 +115,7 @@ void orc_rotate(double alpha, const double n[3], const double u[3], double out[3
 /* Collision of step t on already streamed velocities v, given the sort.
  * x (post-stream positions) is read only with p->amc (it may be NULL
  * otherwise); cell_out (optional) receives ORC_CELL_STRIDE doubles per cell.
- * Lees-Edwards (p->le_u) also reads x.  Returns -2 for amc with walls or
+ * Lees-Edwards (p->le_u) also reads x.  Returns -2 for amc with no-slip walls or
  * without x, for le_u with walls, amc or without x, -3 (p->fixed) for a summand
  * outside the fixed-point range |x| < 2^37. */
 int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, double* v,

@@ -89,6 +89,7 @@ FAST_PINS = [
     "test_observables_against_fsum", "test_reorder_is_gather", "test_philox_matches_rocrand",
     "test_amc_conserves_angular_momentum", "test_amc_correction_is_rigid_rotation",
     "test_amc_alpha_zero_is_identity", "test_amc_refused_with_walls", "test_amc_with_thermostat",
+    "test_amc_with_slip_walls_conserves_angular_momentum",
     "test_fixed_sums_exact", "test_fixed_sums_order_independent", "test_fixed_sums_range",
     "test_moving_wall_bounce_is_galilean", "test_slip_walls_reflect_specularly",
     "test_slip_walls_exert_no_tangential_force", "test_couette_profile",

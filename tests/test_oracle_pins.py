@@ -629,14 +629,42 @@ def test_amc_alpha_zero_is_identity(orc):
 
 
 def test_amc_refused_with_walls(orc):
-    """SRD+a is taken to be defined for periodic boxes (phantom particles carry
-    no positions); the oracle refuses walls and a missing x."""
+    """SRD+a is taken to be defined for periodic boxes and slip walls (phantom
+    particles carry no positions); the oracle refuses no-slip walls and a
+    missing x."""
     x, v = synth.box_state((4, 4, 4), seed=3)
     perm, off = orc.sort(orc.keys(orc.Params(L=(4, 4, 4)), 0, x), 64)
     with pytest.raises(ValueError):
         orc.collide(orc.Params(L=(4, 4, 4), amc=True), 0, v, perm, off)
     with pytest.raises(ValueError):
         orc.step(orc.Params(L=(4, 4, 4), amc=True, walls=True), 0, x, v)
+    orc.step(orc.Params(L=(4, 4, 4), amc=True, walls=True, slip=True), 0, x, v)
+
+
+def test_amc_with_slip_walls_conserves_angular_momentum(orc):
+    """Eqs. 3-4 next to slip walls (cut cells hold fluid particles only): per
+    cell, momentum and angular momentum about the centre of mass are kept."""
+    L = (6, 6, 5)
+    t = 3
+    pa = orc.Params(L=L, walls=True, slip=True, amc=True, seed=19)
+    x, v = synth.box_state(L, seed=23)
+    v *= 2.0
+    xs, vs, nb = orc.stream(pa, x, v)
+    assert nb > 20
+    key = orc.keys(pa, t, xs)
+    perm, off = orc.sort(key, pa.ncells)
+    va = orc.collide(pa, t, vs, perm, off, x=xs)
+    y = xs + orc.shift(pa, t)[:, None]
+    fr = y - np.floor(y)
+    checked = 0
+    for c in np.nonzero(np.diff(off) >= 2)[0]:
+        idx = perm[off[c]:off[c + 1]]
+        r = fr[:, idx] - fr[:, idx].mean(axis=1, keepdims=True)
+        scale = np.abs(vs[:, idx]).sum()
+        assert np.abs(_cell_L(r, va[:, idx]) - _cell_L(r, vs[:, idx])).max() <= 1e-12 * scale
+        assert np.abs(va[:, idx].sum(axis=1) - vs[:, idx].sum(axis=1)).max() <= 1e-13 * scale
+        checked += 1
+    assert checked > 100
 
 
 def test_amc_with_thermostat(orc):
