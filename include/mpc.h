@@ -74,7 +74,8 @@ enum {
                        scaled; kappa scales the corrected relative velocities
                        D u_i + omega x r_ic so that their kinetic energy equals the
                        drawn E_k (angular momentum is then scaled by kappa).
-                       Periodic boxes only: with MPC_WALLS_Z -> MPC_EINVAL           */
+                       Periodic boxes or slip walls: with MPC_WALLS_Z and without
+                       MPC_SLIP -> MPC_EINVAL (phantoms carry no positions)       */
   MPC_SLIP = 16u,    /* with MPC_WALLS_Z: slip walls (Sec. II, Boundary conditions):
                        specular reflection (z and v_z mirrored, v_x, v_y kept) and no
                        phantom particles.  Without MPC_WALLS_Z -> MPC_EINVAL         */

@@ -1997,8 +1997,9 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   if (err) atomicOr(&d.ctrl->err, err);
 }
 
-// Runtime flags (form, walls, thermostat, SRD+a, fixed-point sums) -> the
-// k_collide instantiation.  SRD+a next to walls is not built.
+// Runtime flags (form, walls, thermostat, SRD+a, fixed-point sums,
+// Lees-Edwards) -> the k_collide instantiation.  SRD+a next to walls runs
+// with slip walls only (the host refuses it with no-slip walls).
 struct CollideLaunchOp {
   template <int F, bool W, bool M, bool A, bool X, bool E>
   static hipError_t run(const Dev& d, const Launch& l, int*) {
@@ -2026,12 +2027,8 @@ static hipError_t collide_pick_e(const Dev& d, const Launch& l, int* n) {
 }
 template <class Op, int F, bool W, bool M, bool A>
 static hipError_t collide_pick_x(const Dev& d, const Launch& l, int* n) {
-  if constexpr (A && W) {
-    return hipErrorInvalidValue;
-  } else {
-    return l.fixed ? collide_pick_e<Op, F, W, M, A, true>(d, l, n)
-                   : collide_pick_e<Op, F, W, M, A, false>(d, l, n);
-  }
+  return l.fixed ? collide_pick_e<Op, F, W, M, A, true>(d, l, n)
+                 : collide_pick_e<Op, F, W, M, A, false>(d, l, n);
 }
 template <class Op, int F, bool W, bool M>
 static hipError_t collide_pick_a(const Dev& d, const Launch& l, int* n) {

@@ -67,8 +67,8 @@ def test_workspace_planning_and_validation_on_host():
 
 
 def test_amc_flag_validation_on_host():
-    """SRD+a (MPC_AMC) is accepted for periodic boxes, with or without the
-    thermostat, and refused with MPC_WALLS_Z."""
+    """SRD+a (MPC_AMC) is accepted for periodic boxes and slip walls, with or
+    without the thermostat, and refused with no-slip walls."""
     import paper_2406_15236_amd as m
     import synth
     if not os.path.exists(m.LIB):
@@ -79,6 +79,7 @@ def test_amc_flag_validation_on_host():
     with pytest.raises(m.MPCError) as e:
         m.workspace_bytes(m.make_params(dict(c1, amc=True, walls=True)))
     assert e.value.code == m.EINVAL
+    assert m.workspace_bytes(m.make_params(dict(c1, amc=True, walls=True, slip=True))) > 0
     with pytest.raises(m.MPCError) as e:
         m.workspace_bytes(m.make_params(c1, flags=16))
     assert e.value.code == m.EINVAL

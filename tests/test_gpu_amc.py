@@ -178,6 +178,7 @@ def test_amc_conserves_angular_momentum_on_gpu(mpc, form):
 
 
 def test_amc_with_walls_refused(mpc):
+    """No-slip walls would need phantom positions: refused (slip walls are fine)."""
     box = box_of((8, 8, 8), walls=True)
     with pytest.raises(mpc.MPCError) as e:
         mpc.Sim(box)
@@ -195,3 +196,41 @@ def test_amc_thermostat_relaxes_temperature(mpc):
         T = sim.observables()["T"]
     print(f"amc+mbs: T after 30 steps from kT = 2: {T:.4f}")
     assert abs(T - 1.0) < 0.02
+
+
+@pytest.mark.parametrize("form,mbs", [("fp64", False), ("fp64", True), ("split", True)])
+def test_amc_slip_walls_one_step(mpc, form, mbs):
+    """SRD+a next to slip walls (no phantoms), with gravity along x."""
+    L = (12, 10, 8)
+    box = box_of(L, seed=15, mbs=mbs, walls=True, slip=True, g=(1e-3, 0.0, 0.0))
+    x, v = synth.box_state(L, seed=25)
+    v *= 2.0
+    t0 = 6
+    print(f"case amc slip walls form={form} mbs={mbs}", flush=True)
+    with mpc.Sim(box, form=form, reorder_every=0) as sim:
+        sim.set_state(x, v)
+        x0, v0 = sim.get_state()
+        sim.set_step(t0)
+        sim.step(1)
+        x1, v1 = sim.get_state()
+        kg, pg, og = sim.get_binning()
+    p = orc.Params(L=L, h=box["h"], alpha=box["alpha"], kT=box["kT"], mass=box["mass"],
+                   density=box["density"], seed=box["seed"], mbs=mbs, walls=True, slip=True,
+                   amc=True, g=box["g"])
+    xs, vs, nb = orc.stream(p, x0, v0)
+    assert nb > 50
+    if form == "fp64":
+        np.testing.assert_array_equal(x1, xs)
+    ko = orc.keys(p, t0, x1)
+    np.testing.assert_array_equal(kg, ko)
+    po, oo = orc.sort(ko, p.ncells)
+    np.testing.assert_array_equal(og, oo)
+    vo = orc.collide(p, t0, vs, po, oo, x=x1)
+    e = rel_err(v1, vo, box)
+    if form == "fp64":
+        cond = cell_cond(ko, oo, po, frame(p, t0, x1))
+        tol = 1e-12 + 64 * EPS * cond
+    else:
+        tol = 2e-6
+    print(f"amc slip walls {form}: max e = {e.max():.3e}")
+    assert np.all(e <= tol)
