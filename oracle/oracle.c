@@ -520,7 +520,7 @@ static void amc_cell(const orc_params* p, const double s[3], int64_t n, const do
 int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, double* v,
                 const uint32_t* perm, const uint32_t* offset, int64_t ncell, double* cell_out) {
   if (p->amc && ((p->walls && !p->slip) || !x)) return -2;
-  if (p->le_u != 0.0 && (p->walls || p->amc || !x)) return -2;
+  if (p->le_u != 0.0 && (p->walls || !x)) return -2;
   int bad = 0; /* a fixed-point summand out of range */
   const double m = p->mass;
   double* v0 = NULL; /* pre-collision velocities (SRD+a) */
@@ -531,6 +531,20 @@ int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, dou
   const double ca = cos(p->alpha), sa = sin(p->alpha), omc = 1.0 - ca;
   double s[3];
   orc_shift(p, t, s);
+  /* SRD+a with Lees-Edwards shear: the positions of the particles that a cell
+   * across a z face takes as their image, x -/+ d (the velocities get their
+   * frame change in the cell loop) */
+  double* xa = (double*)x;
+  if (p->amc && p->le_u != 0.0) {
+    xa = (double*)malloc((size_t)3 * (size_t)(n > 0 ? n : 1) * sizeof(double));
+    memcpy(xa, x, (size_t)3 * (size_t)n * sizeof(double));
+    double d = le_offset(p, t + 1);
+    for (int64_t i = 0; i < n; ++i) {
+      int side = le_side(p, x[2 * n + i], s[2]);
+      if (side < 0) xa[i] = x[i] - d;
+      if (side > 0) xa[i] = x[i] + d;
+    }
+  }
   const int64_t plane = (int64_t)p->L[0] * p->L[1];
   enum { PMAX = 127 };
   double vp[3 * PMAX];
@@ -565,6 +579,8 @@ int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, dou
         int side = le_side(p, x[2 * n + i], s[2]);
         if (side < 0) v[i] = v[i] - p->le_u;
         if (side > 0) v[i] = v[i] + p->le_u;
+        if (v0 && side < 0) v0[i] = v0[i] - p->le_u;
+        if (v0 && side > 0) v0[i] = v0[i] + p->le_u;
       }
     }
 
@@ -638,7 +654,7 @@ int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, dou
       }
     }
     if (p->amc) {
-      amc_cell(p, s, n, x, v0, v, perm, b, e, V, ax, ca, sa, omc, &bad);
+      amc_cell(p, s, n, xa, v0, v, perm, b, e, V, ax, ca, sa, omc, &bad);
       /* MBS with SRD+a: kappa sets the cell's relative kinetic energy after
        * the corrected collision to the drawn E_k */
       orc_sum K2s = sum_new(p);
@@ -678,6 +694,7 @@ int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, dou
   }
 
   free(v0);
+  if (xa != x) free(xa);
   if (p->g[0] != 0.0 || p->g[1] != 0.0 || p->g[2] != 0.0) {
     for (int k = 0; k < 3; ++k) {
       double gh = p->g[k] * p->h;

@@ -116,7 +116,7 @@ void orc_rotate(double alpha, const double n[3], const double u[3], double out[3
  * x (post-stream positions) is read only with p->amc (it may be NULL
  * otherwise); cell_out (optional) receives ORC_CELL_STRIDE doubles per cell.
  * Lees-Edwards (p->le_u) also reads x.  Returns -2 for amc with no-slip walls or
- * without x, for le_u with walls, amc or without x, -3 (p->fixed) for a summand
+ * without x, for le_u with walls or without x, -3 (p->fixed) for a summand
  * outside the fixed-point range |x| < 2^37. */
 int orc_collide(const orc_params* p, uint64_t t, int64_t n, const double* x, double* v,
                 const uint32_t* perm, const uint32_t* offset, int64_t ncell,

@@ -73,6 +73,9 @@ MUTANTS = {
                            "double xi = c[2] >= p->L[2] ? x[i] + d : x[i] - d;"),
     "le_frame_not_restored": ("if (side < 0) v[i] = v[i] + p->le_u;", "if (side < 0) v[i] = v[i];"),
     "le_no_collision_frame": ("const int le = p->le_u != 0.0 && ntot >= 2;", "const int le = 0;"),
+    "le_amc_torque_lab_frame": ("if (v0 && side < 0) v0[i] = v0[i] - p->le_u;",
+                                "if (0) v0[i] = v0[i] - p->le_u;"),
+    "le_amc_positions_unmapped": ("      if (side < 0) xa[i] = x[i] - d;", "      if (side < 0) xa[i] = x[i];"),
     "fixed_rounds_terms": ("a->s += (__int128)(x * 0x1p80);", "a->s += (__int128)nearbyint(x * 0x1p80);"),
     "fixed_scale_back": ("(double)a->s * 0x1p-80", "(double)a->s * 0x1p-79"),
     "fixed_range": ("} else if (fabs(x) < 0x1p37) {", "} else if (fabs(x) < 0x1p60) {"),
@@ -95,6 +98,7 @@ FAST_PINS = [
     "test_slip_walls_exert_no_tangential_force", "test_couette_profile",
     "test_lees_edwards_stream", "test_lees_edwards_keys_use_the_image",
     "test_lees_edwards_momentum_budget", "test_lees_edwards_shear_profile",
+    "test_amc_lees_edwards_conserves_angular_momentum",
 ]
 
 PARAMS = {"test_keys_exact_floor": [{"walls": False}, {"walls": True}],

@@ -967,3 +967,37 @@ def test_lees_edwards_shear_profile(orc):
     slope, icpt = np.polyfit(z, acc / cnt, 1)
     print(f"Lees-Edwards: slope {slope:.4f} (U/L_z = {U / L[2]:.4f})")
     assert abs(slope / (U / L[2]) - 1) < 0.05
+
+
+def test_amc_lees_edwards_conserves_angular_momentum(orc):
+    """SRD+a under Lees-Edwards shear: a cell across a z face holds particles
+    seen as their images (x -/+ d, v_x -/+ U); in that frame each cell keeps
+    its momentum and its angular momentum about the centre of mass."""
+    L = (6, 6, 6)
+    U, t = 0.7, 5
+    p = orc.Params(L=L, le_u=U, amc=True, seed=31)
+    x, v = synth.box_state(L, seed=67)
+    xs, vs, _ = orc.stream(p, x, v, t=t)
+    key = orc.keys(p, t, xs)
+    perm, off = orc.sort(key, p.ncells)
+    va = orc.collide(p, t, vs, perm, off, x=xs)
+    s = orc.shift(p, t)
+    d = _le_offset(U, t + 1, p.h, L[0])
+    cz = np.floor(xs[2] + s[2])
+    side = np.where(cz < 0, 1.0, np.where(cz >= L[2], -1.0, 0.0))
+    xm = xs.copy()
+    xm[0] += side * d
+    y = xm + s[:, None]
+    fr = y - np.floor(y)
+    vf0, vf1 = vs.copy(), va.copy()
+    vf0[0] += side * U
+    vf1[0] += side * U
+    crossing = 0
+    for c in np.nonzero(np.diff(off) >= 2)[0]:
+        idx = perm[off[c]:off[c + 1]]
+        crossing += bool(np.any(side[idx] != 0))
+        r = fr[:, idx] - fr[:, idx].mean(axis=1, keepdims=True)
+        scale = np.abs(vf0[:, idx]).sum()
+        assert np.abs(_cell_L(r, vf1[:, idx]) - _cell_L(r, vf0[:, idx])).max() <= 1e-12 * scale
+        assert np.abs(vf1[:, idx].sum(axis=1) - vf0[:, idx].sum(axis=1)).max() <= 1e-13 * scale
+    assert crossing > 10
