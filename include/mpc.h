@@ -133,8 +133,8 @@ typedef struct {
                              through a z face re-enters shifted by -/+ that offset
                              with v_x -/+ le_u; a collision cell across a z face is
                              formed with the image on the other side, in its velocity
-                             frame.  0 = plain periodic.  With MPC_WALLS_Z or MPC_AMC
-                             -> MPC_EINVAL                                          */
+                             frame (with MPC_AMC also with its image positions).
+                             0 = plain periodic.  With MPC_WALLS_Z -> MPC_EINVAL  */
 } mpc_params;
 
 /* Observables of one box (FP64, compensated sums over the particles). */

@@ -65,8 +65,8 @@ int validate(const mpc_params* p, int32_t nbox, std::string* why) {
     if (q.wall_u != 0.0 && (!(q.flags & MPC_WALLS_Z) || (q.flags & MPC_SLIP)))
       return bad("wall_u needs no-slip walls (MPC_WALLS_Z without MPC_SLIP)");
     if (!isfinite(q.le_u)) return bad("le_u must be finite");
-    if (q.le_u != 0.0 && (q.flags & (MPC_WALLS_Z | MPC_AMC)))
-      return bad("le_u (Lees-Edwards) needs a periodic box without MPC_AMC");
+    if (q.le_u != 0.0 && (q.flags & MPC_WALLS_Z))
+      return bad("le_u (Lees-Edwards) needs a periodic box (no MPC_WALLS_Z)");
     if ((q.flags & MPC_AMC) && (q.flags & MPC_WALLS_Z) && !(q.flags & MPC_SLIP))
       return bad("MPC_AMC is defined for periodic boxes and slip walls (MPC_SLIP)");
     if (q.form != p[0].form || q.flags != p[0].flags || q.reorder_every != p[0].reorder_every)

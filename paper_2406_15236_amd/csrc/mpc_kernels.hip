@@ -1180,7 +1180,8 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
                           const typename Form<F>::Xs* __restrict__ sx1,
                           const typename Form<F>::Xs* __restrict__ sx2, const double (&s)[3],
                           uint32_t b, uint32_t e, uint32_t half, bool valid,
-                          typename CellRec<F, A>::T* out, uint32_t& err) {
+                          typename CellRec<F, A>::T* out, uint32_t& err,
+                          const int8_t* __restrict__ sside, double dle) {
   const uint32_t nf = valid ? e - b : 0u;
   const uint32_t mid = b + (nf + 1) / 2;
   const uint32_t qb = half ? mid : b, qe = valid ? (half ? e : mid) : b;
@@ -1318,10 +1319,20 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
   // omega = 0.  Both lanes of the pair build identical totals.
   double rc[3] = {0.0, 0.0, 0.0}, om[3] = {0.0, 0.0, 0.0};
   if constexpr (A) {
+    // cell-frame x; under Lees-Edwards shear a particle taken as its image
+    // (sside = -1 / +1) sits at x - d / x + d
+    auto fx = [&](uint32_t q) -> double {
+      double xq = (double)sx0[q];
+      if (sside) {
+        if (sside[q] < 0) xq = xq - dle;
+        if (sside[q] > 0) xq = xq + dle;
+      }
+      return frame_pos(xq, s[0]);
+    };
     if constexpr (X) {
       Fix fr[3] = {{0ull, 0ull}, {0ull, 0ull}, {0ull, 0ull}};
       for (uint32_t q = qb; q < qe; ++q) {
-        fix_add(fr[0], frame_pos(sx0[q], s[0]), err);
+        fix_add(fr[0], fx(q), err);
         fix_add(fr[1], frame_pos(sx1[q], s[1]), err);
         fix_add(fr[2], frame_pos(sx2[q], s[2]), err);
       }
@@ -1332,7 +1343,7 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
       }
     } else {
       for (uint32_t q = qb; q < qe; ++q) {
-        rc[0] = rc[0] + frame_pos(sx0[q], s[0]);
+        rc[0] = rc[0] + fx(q);
         rc[1] = rc[1] + frame_pos(sx1[q], s[1]);
         rc[2] = rc[2] + frame_pos(sx2[q], s[2]);
       }
@@ -1359,7 +1370,7 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
         Fix f5[5] = {{0ull, 0ull}, {0ull, 0ull}, {0ull, 0ull}, {0ull, 0ull}, {0ull, 0ull}};
         const int a1 = a == 2 ? 0 : a + 1;
         for (uint32_t q = qb; q < qe; ++q) {
-          const double r[3] = {frame_pos(sx0[q], s[0]) - rc[0], frame_pos(sx1[q], s[1]) - rc[1],
+          const double r[3] = {fx(q) - rc[0], frame_pos(sx1[q], s[1]) - rc[1],
                                frame_pos(sx2[q], s[2]) - rc[2]};
           const double u[3] = {(double)sv0[q] - V[0], (double)sv1[q] - V[1],
                                (double)sv2[q] - V[2]};
@@ -1390,7 +1401,7 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
       }
     } else {
     for (uint32_t q = qb; q < qe; ++q) {
-      const double r[3] = {frame_pos(sx0[q], s[0]) - rc[0], frame_pos(sx1[q], s[1]) - rc[1],
+      const double r[3] = {fx(q) - rc[0], frame_pos(sx1[q], s[1]) - rc[1],
                            frame_pos(sx2[q], s[2]) - rc[2]};
       const double u[3] = {(double)sv0[q] - V[0], (double)sv1[q] - V[1], (double)sv2[q] - V[2]};
 #pragma unroll
@@ -1547,6 +1558,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   __shared__ Xs s_x[3][kTileCap];        // streamed positions (offsets), canonical order
   __shared__ uint32_t s_c[Fm::kHasCell ? kTileCap : 1];
   __shared__ typename CellRec<F, A>::T s_cell[kTileMaxCells];
+  __shared__ int8_t s_side[E ? kTileCap : 1];  // Lees-Edwards side of each slot
   __shared__ double s_sh[8];  // shifts of t and t + 1; Lees-Edwards offsets of t + 1, t + 2
   // next-step window of the tile: cells x0-1 .. x0+nc of the rows (y0 +- 1,
   // z0 +- 1), plus one entry for particles that leave it; per pass: counts,
@@ -1757,11 +1769,14 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             const uint32_t id = track ? s_rk[q] : i;
             const uint32_t qc = b + rank_in_segment(track ? s_rk : s_idx, b, e, id);
             Fm::template stream<W>(p[k], v[k], B, s_sh[6], E && B.le);
-            if (E && B.le && e - b >= 2u) {
-              // a colliding cell across a z face: its image's velocity frame
-              const int side = Fm::le_side(p[k], s_sh[2], B);
-              if (side < 0) v[k].v[0] = (Vs)((double)v[k].v[0] - B.leu);
-              if (side > 0) v[k].v[0] = (Vs)((double)v[k].v[0] + B.leu);
+            if constexpr (E) {
+              const int side = B.le ? Fm::le_side(p[k], s_sh[2], B) : 0;
+              s_side[qc] = (int8_t)side;
+              if (e - b >= 2u) {
+                // a colliding cell across a z face: its image's velocity frame
+                if (side < 0) v[k].v[0] = (Vs)((double)v[k].v[0] - B.leu);
+                if (side > 0) v[k].v[0] = (Vs)((double)v[k].v[0] + B.leu);
+              }
             }
             Fm::to_lds(p[k], s_x[0], s_x[1], s_x[2], s_c, qc);
             s_v[0][qc] = v[k].v[0];
@@ -1796,7 +1811,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
         cell_work<F, W, M, A, X>(B, lkey0 + c, s_sh[2], cd,
                                  W ? d.phs + T.c0 + (valid ? c : 0u) : nullptr, s_v[0], s_v[1],
                                  s_v[2], s_x[0], s_x[1], s_x[2], s_t, b, e, lane & 1u, valid,
-                                 &s_cell[j], err);
+                                 &s_cell[j], err, E ? s_side : nullptr, s_sh[6]);
       }
       wave_sync();
 
@@ -1826,17 +1841,21 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
               if constexpr (A) {
                 // omega x r_ic in FP64 (|omega| is large in ill-conditioned
                 // cells), added to the FP32 rotation result with one rounding
-                const double r[3] = {frame_pos(s_x[0][q], s_sh[0]) - C.rc[0],
+                double xq = (double)s_x[0][q];
+                if constexpr (E) {
+                  if (s_side[q] < 0) xq = xq - s_sh[6];
+                  if (s_side[q] > 0) xq = xq + s_sh[6];
+                }
+                const double r[3] = {frame_pos(xq, s_sh[0]) - C.rc[0],
                                      frame_pos(s_x[1][q], s_sh[1]) - C.rc[1],
                                      frame_pos(s_x[2][q], s_sh[2]) - C.rc[2]};
                 v.v[0] = (float)((double)v.v[0] + (C.om[1] * r[2] - C.om[2] * r[1]));
                 v.v[1] = (float)((double)v.v[1] + (C.om[2] * r[0] - C.om[0] * r[2]));
                 v.v[2] = (float)((double)v.v[2] + (C.om[0] * r[1] - C.om[1] * r[0]));
               }
-              if (E && B.le) {  // leave the Lees-Edwards image frame
-                const int side = Fm::le_side(p, s_sh[2], B);
-                if (side < 0) v.v[0] = (float)((double)v.v[0] + B.leu);
-                if (side > 0) v.v[0] = (float)((double)v.v[0] - B.leu);
+              if constexpr (E) {  // leave the Lees-Edwards image frame
+                if (s_side[q] < 0) v.v[0] = (float)((double)v.v[0] + B.leu);
+                if (s_side[q] > 0) v.v[0] = (float)((double)v.v[0] - B.leu);
               }
             }
             if (B.grav) {
@@ -1853,17 +1872,21 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
 #pragma unroll
               for (int a = 0; a < 3; ++a) w[a] = C.V[a] + C.kappa * r[a];
               if constexpr (A) {
-                const double rr[3] = {frame_pos(s_x[0][q], s_sh[0]) - C.rc[0],
+                double xq = (double)s_x[0][q];
+                if constexpr (E) {
+                  if (s_side[q] < 0) xq = xq - s_sh[6];
+                  if (s_side[q] > 0) xq = xq + s_sh[6];
+                }
+                const double rr[3] = {frame_pos(xq, s_sh[0]) - C.rc[0],
                                       frame_pos(s_x[1][q], s_sh[1]) - C.rc[1],
                                       frame_pos(s_x[2][q], s_sh[2]) - C.rc[2]};
                 w[0] = w[0] + (C.om[1] * rr[2] - C.om[2] * rr[1]);
                 w[1] = w[1] + (C.om[2] * rr[0] - C.om[0] * rr[2]);
                 w[2] = w[2] + (C.om[0] * rr[1] - C.om[1] * rr[0]);
               }
-              if (E && B.le) {  // leave the Lees-Edwards image frame
-                const int side = Fm::le_side(p, s_sh[2], B);
-                if (side < 0) w[0] = w[0] + B.leu;
-                if (side > 0) w[0] = w[0] - B.leu;
+              if constexpr (E) {  // leave the Lees-Edwards image frame
+                if (s_side[q] < 0) w[0] = w[0] + B.leu;
+                if (s_side[q] > 0) w[0] = w[0] - B.leu;
               }
             }
             if (B.grav) {
@@ -2015,10 +2038,10 @@ struct CollideOccOp {
                                                         kCollideThreads, 0);
   }
 };
-// Lees-Edwards (E) is built for periodic boxes without SRD+a only.
+// Lees-Edwards (E) is built for periodic boxes only.
 template <class Op, int F, bool W, bool M, bool A, bool X>
 static hipError_t collide_pick_e(const Dev& d, const Launch& l, int* n) {
-  if constexpr (W || A) {
+  if constexpr (W) {
     return l.le ? hipErrorInvalidValue : Op::template run<F, W, M, A, X, false>(d, l, n);
   } else {
     return l.le ? Op::template run<F, W, M, A, X, true>(d, l, n)

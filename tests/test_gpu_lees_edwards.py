@@ -7,6 +7,8 @@ conditions; mpc_params.le_u).
   * Momentum budget on the GPU: a step changes the total x momentum only by
     U (n_down - n_up), the face crossings.
   * The steady shear profile: v_x(z) linear with slope U / L_z.
+  * SRD+a under the shear against the oracle (image positions and velocities
+    in the cells across the z faces).
 """
 import math
 
@@ -160,6 +162,53 @@ def test_lees_edwards_flag_validation(mpc):
     with pytest.raises(mpc.MPCError) as e:
         mpc.Sim(box_of((8, 8, 8), 0.3, walls=True))
     assert e.value.code == mpc.EINVAL
-    with pytest.raises(mpc.MPCError) as e:
-        mpc.Sim(box_of((8, 8, 8), 0.3, amc=True))
-    assert e.value.code == mpc.EINVAL
+
+
+EPS = 2.0 ** -52
+
+
+@pytest.mark.parametrize("form,mbs", [("fp64", False), ("fp64", True), ("split", True)])
+def test_lees_edwards_with_amc_one_step(mpc, form, mbs):
+    """SRD+a under Lees-Edwards shear: image positions and velocities in the
+    cells across the z faces.  FP64 e <= 1e-12 + 64 eps cond(I_c)."""
+    L = (12, 10, 8)
+    U, t0 = 0.7, 9
+    box = box_of(L, U, seed=17, mbs=mbs, amc=True)
+    x, v = synth.box_state(L, seed=29)
+    v *= 2.0
+    print(f"case le amc form={form} mbs={mbs}", flush=True)
+    with mpc.Sim(box, form=form) as sim:
+        sim.set_state(x, v)
+        x0, v0 = sim.get_state()
+        sim.set_step(t0)
+        sim.step(1)
+        x1, v1 = sim.get_state()
+        kg, pg, og = sim.get_binning()
+    p = orc.Params(L=L, h=box["h"], alpha=box["alpha"], kT=box["kT"], mass=box["mass"],
+                   density=box["density"], seed=box["seed"], mbs=mbs, amc=True, le_u=U)
+    xs, vs, _ = orc.stream(p, x0, v0, t=t0)
+    if form == "fp64":
+        np.testing.assert_array_equal(x1, xs)
+    ko = orc.keys(p, t0, x1)
+    np.testing.assert_array_equal(kg, ko)
+    po, oo = orc.sort(ko, p.ncells)
+    vo = orc.collide(p, t0, vs, po, oo, x=x1)
+    e = rel_err(v1, vo, box)
+    tol = 2e-6
+    if form == "fp64":
+        s = orc.shift(p, t0)
+        d = (U * (t0 + 1) * box["h"]) % L[0]
+        cz = np.floor(x1[2] + s[2])
+        side = np.where(cz < 0, 1.0, np.where(cz >= L[2], -1.0, 0.0))
+        xm = x1.copy()
+        xm[0] += side * d
+        y = xm + s[:, None]
+        fr = y - np.floor(y)
+        cond = np.ones(x1.shape[1])
+        for c in np.nonzero(np.diff(oo) >= 3)[0]:
+            idx = po[oo[c]:oo[c + 1]]
+            r = fr[:, idx] - fr[:, idx].mean(axis=1, keepdims=True)
+            cond[idx] = np.linalg.cond((r * r).sum() * np.eye(3) - r @ r.T)
+        tol = 1e-12 + 64 * EPS * cond
+    print(f"le amc {form}: max e = {e.max():.3e}")
+    assert np.all(e <= tol)
