@@ -83,3 +83,22 @@ def test_amc_flag_validation_on_host():
     with pytest.raises(m.MPCError) as e:
         m.workspace_bytes(m.make_params(c1, flags=16))
     assert e.value.code == m.EINVAL
+
+
+def test_boundary_parameter_validation_on_host():
+    """Slip walls need walls; wall_u needs no-slip walls; le_u needs a periodic
+    box; non-finite wall_u or le_u are refused."""
+    import paper_2406_15236_amd as m
+    import synth
+    if not os.path.exists(m.LIB):
+        pytest.skip("library not built")
+    c5 = dict(synth.config("C5"), L=(16, 16, 8))
+    c1 = synth.config("C1")
+    assert m.workspace_bytes(m.make_params(dict(c5, slip=True))) > 0
+    assert m.workspace_bytes(m.make_params(dict(c5, uwall=0.2))) > 0
+    assert m.workspace_bytes(m.make_params(dict(c1, le_u=0.5, amc=True, fixed=True))) > 0
+    for bad in (dict(c1, slip=True), dict(c5, slip=True, uwall=0.1), dict(c1, uwall=0.1),
+                dict(c5, le_u=0.5), dict(c1, le_u=float("nan")), dict(c5, uwall=float("inf"))):
+        with pytest.raises(m.MPCError) as e:
+            m.workspace_bytes(m.make_params(bad))
+        assert e.value.code == m.EINVAL
