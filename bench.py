@@ -282,7 +282,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU path is a design in DESIGN.md, not built.", file=sys.stderr)
+              "the multi-GPU path is not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch

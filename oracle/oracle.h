@@ -17,8 +17,7 @@
  *   Sec. II (External fields) constant gravity
  *   Sec. III.B.3 (Permanent exchange) reorder by cell -> orc_reorder
  *   Sec. III.C      fixed-point cell sums (optional)  -> orc_collide
- * Where the paper is silent the reading used is listed in the design doc under
- * "Readings of the paper"; each function below names the reading it takes.
+ * Where the paper is silent, each function below states the reading it takes.
  *
  * Units: lengths in units of the cell size a (so a = 1 here); the caller
  * converts.  Arrays are SoA: x[0..n) is the x component, x[n..2n) y,
@@ -71,7 +70,9 @@ enum { ORC_TAG_SHIFT = 1, ORC_TAG_AXIS = 2, ORC_TAG_THERMO = 3, ORC_TAG_PHANTOM 
 /* Philox4x32-10 block function. */
 void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
-/* Uniform / normal conversions of Philox words. */
+/* Uniform conversions of Philox words: u24 = (w >> 8) 2^-24 in [0, 1);
+ * u53 = (a:b top 53 bits) 2^-53 in [0, 1); u53_open = (m + 1/2) 2^-52 with
+ * m the top 52 bits, in (0, 1); u32_open = (w + 1/2) 2^-32 in (0, 1). */
 double orc_u24(uint32_t w);
 double orc_u53(uint32_t a, uint32_t b);
 double orc_u53_open(uint32_t a, uint32_t b);
