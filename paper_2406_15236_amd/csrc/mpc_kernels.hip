@@ -870,10 +870,19 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(Dev d, uint32_t nblk, ui
   if (blockIdx.x == nblk - 1 && threadIdx.x == kThreads - 1)
     d.offset[(uint64_t)nblk * kScanBlock] = run;
 
-  // per-cell draws for step t
-  if (base >= ctot) return;
+  // per-cell draws for step t; the counts go through LDS so that consecutive
+  // lanes draw (and store the 32-byte records of) consecutive cells
+  __shared__ uint4 s_cnt[kScanBlock / 4];
+#pragma unroll
+  for (int k = 0; k < kScanItems / 4; ++k)
+    s_cnt[threadIdx.x * (kScanItems / 4) + k] =
+        make_uint4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+  __syncthreads();
+  const uint64_t blk0 = (uint64_t)blockIdx.x * kScanBlock;
+  if (blk0 + threadIdx.x >= ctot) return;
+  const uint32_t* cnt = (const uint32_t*)s_cnt;
   const uint64_t t = as_const(d.ctrl)->step;
-  uint32_t b = box_of_cell(d.boxes, nbox, (uint32_t)base);
+  uint32_t b = box_of_cell(d.boxes, nbox, (uint32_t)(blk0 + threadIdx.x));
   double sz = 0.0;
   if (W) {
     double sh[3];
@@ -882,7 +891,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(Dev d, uint32_t nblk, ui
   }
 #pragma unroll 1
   for (int k = 0; k < kScanItems; ++k) {
-    const uint32_t c = (uint32_t)base + k;
+    const uint32_t c = (uint32_t)(blk0 + (uint64_t)k * kThreads + threadIdx.x);
     if (c >= ctot) break;
     while (c >= as_const(d.boxes)[b].cbase + as_const(d.boxes)[b].nc) {
       ++b;
@@ -892,10 +901,11 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(Dev d, uint32_t nblk, ui
         sz = sh[2];
       }
     }
-    if (v[k] == 0u) continue;
+    const uint32_t nf = cnt[k * kThreads + threadIdx.x];
+    if (nf == 0u) continue;
     BoxRef B = as_const(d.boxes)[b];
     CellDraw cd;
-    cell_draws<W, M>(B, t, c - B.cbase, v[k], sz, cd);
+    cell_draws<W, M>(B, t, c - B.cbase, nf, sz, cd);
     d.draws[c] = cd;
   }
 }
