@@ -16,7 +16,8 @@ timed region; 200 steps by default).  The same line carries:
                  conserving collision SRD+a in FP64 and split-FP32, FP64
                  with fixed-point (order-independent) cell sums, the
                  256x256x64 channel with slip walls or moving walls, the
-                 256^3 box under Lees-Edwards shear, the
+                 256^3 box under Lees-Edwards shear, 128^3 cells at 50
+                 particles per cell, the
                  cost of each collision feature on 100^3 and the reorder-
                  interval sweep on 128^3;
   cpu_baseline : the single-threaded CPU oracle on a bounded sample.
@@ -271,7 +272,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--forms",
                     default="fp32,split,fp64_sorted_every_step,batched,amc,amc_split,fp64_fixed,"
-                            "walls_slip,walls_couette,lees_edwards,features,reorder_sweep",
+                            "walls_slip,walls_couette,lees_edwards,density50,features,"
+                            "reorder_sweep",
                     help="extra entries besides the FP64 headline (comma list, or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=500)
@@ -443,6 +445,25 @@ def main():
                 forms[form]["collide_traffic_bytes"] = tra["bytes_per_launch"] if tra else None
                 print(f"[{form} C2] {w2 * 1e3 / args.steps:.3f} ms/step collide {c2:.3f} ms",
                       file=sys.stderr)
+            elif form == "density50":
+                # the paper's main-text density: 128^3 cells x 50 particles, FP64,
+                # thermostat, with and without SRD+a
+                out = {}
+                for tag, kw in (("srd", {}), ("amc", {"amc": True})):
+                    dbox = dict(synth.config("C1"), L=(128, 128, 128), density=50.0, mbs=True,
+                                **kw)
+                    n2, w2, k2, o2 = run_box(mpc, torch, dbox, "fp64", R, args.steps,
+                                             args.warmup)
+                    c2 = k2.collide_ms / max(1, k2.collide_launches)
+                    out[tag] = {"value": n2 * args.steps / w2, "unit": "particle-steps/s",
+                                "ms_per_step": w2 * 1e3 / args.steps, "collide_ms": c2,
+                                "collide_achieved_GBs":
+                                    n2 * 2 * STATE_BYTES["fp64"] / (c2 * 1e-3) / 1e9,
+                                "launch": run_box.last_tiling}
+                    print(f"[density50 {tag}] N={n2} {w2 * 1e3 / args.steps:.3f} ms/step "
+                          f"collide {c2:.3f} ms", file=sys.stderr, flush=True)
+                forms[form] = {"workload": f"128^3 cells x 50 particles (104,857,600), FP64, "
+                                           f"thermostat, reorder every {R} steps", "sets": out}
             elif form == "features":
                 forms["features"] = run_features(mpc, torch, synth)
             elif form == "reorder_sweep":
