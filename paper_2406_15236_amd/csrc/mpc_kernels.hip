@@ -1735,6 +1735,8 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
         typename Fm::P p[NS];
         typename Fm::Vv v[NS];
         uint32_t ii[NS], idk[NS];
+        // issue the gathers ahead of other waves' arithmetic
+        __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
           const uint32_t q = lane + k * NT;
@@ -1760,6 +1762,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
           }
           if (lane < Tn.nc) draw_next = d.draws[Tn.c0 + lane];
         }
+        __builtin_amdgcn_s_setprio(0);
         if (track) {
 #pragma unroll
           for (int k = 0; k < NS; ++k) {
@@ -1960,6 +1963,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
       wave_sync();
       // D2: the pass's particles, grouped by next-step cell, into its slots;
       // logical indices: the canonical (cell, index) position on reorder steps
+      __builtin_amdgcn_s_setprio(2);
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
         const uint32_t q = lane + k * NT;
@@ -1987,6 +1991,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
           }
         }
       }
+      __builtin_amdgcn_s_setprio(0);
       // D3: ranks inside the next-step cells (rank base of the entry + place)
       wave_sync();
       {
