@@ -250,3 +250,22 @@ def test_batched_boxes_with_different_boundary_velocities(mpc, kind):
         e = rel_err(outs[i][1], vo, b)
         print(f"{kind} box {i}: max e = {e.max():.3e}")
         assert e.max() <= 1e-12, (i, e.max())
+
+
+def test_lees_edwards_20_steps_graph(mpc):
+    """20 steps replayed from a captured graph (the offset d(t) advances every
+    step) against the oracle run from the same state."""
+    L = (16, 16, 16)
+    U = 0.8
+    box = box_of(L, U, seed=8)
+    x, v = synth.box_state(L, seed=81)
+    with mpc.Sim(box, form="fp64", graph=True) as sim:
+        sim.set_state(x, v)
+        sim.step(20)
+        xg, vg = sim.get_state()
+    xo, vo = orc.run(oparams(box), x, v, 20)
+    d = np.abs(xg - xo)
+    d = np.minimum(d, 16.0 - d)
+    e = rel_err(vg, vo, box)
+    print(f"le 20 steps: max |dx| = {d.max():.3e}, max e = {e.max():.3e}")
+    assert d.max() < 1e-10 and e.max() < 1e-10
