@@ -170,3 +170,25 @@ def test_wall_flag_validation(mpc):
     with pytest.raises(mpc.MPCError) as e:
         mpc.Sim(box_of((8, 8, 8), slip=True, uwall=0.1))
     assert e.value.code == mpc.EINVAL
+
+
+@pytest.mark.parametrize("kw", [dict(slip=True, g=(2e-3, 0.0, 0.0)), dict(uwall=0.3),
+                                dict(uwall=0.3, fixed=True)])
+def test_walls_20_steps_graph(mpc, kw):
+    """20 steps replayed from a captured graph against the oracle run."""
+    L = (12, 10, 8)
+    box = box_of(L, seed=10, **kw)
+    x, v = synth.box_state(L, seed=83)
+    with mpc.Sim(box, form="fp64", graph=True) as sim:
+        sim.set_state(x, v)
+        sim.step(20)
+        xg, vg = sim.get_state()
+    p = oparams(box)
+    p.fixed = bool(kw.get("fixed", False))
+    xo, vo = orc.run(p, x, v, 20)
+    d = np.abs(xg - xo)
+    for k in range(2):
+        d[k] = np.minimum(d[k], L[k] - d[k])
+    e = rel_err(vg, vo, box)
+    print(f"walls {kw} 20 steps: max |dx| = {d.max():.3e}, max e = {e.max():.3e}")
+    assert d.max() < 1e-10 and e.max() < 1e-10
