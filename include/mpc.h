@@ -102,7 +102,11 @@ enum {
   MPC_ESTATE = -5    /* a particle left the box or became non-finite                    */
 };
 
-#define MPC_MAX_CELL_PARTICLES 1024
+/* Largest number of particles one collision cell may hold in a step: a cell
+ * is collided in one on-chip pass.  A fuller cell is streamed and re-binned
+ * but not collided in that step, and the next synchronising call returns
+ * MPC_ERANGE (the trajectory is then no longer the method's). */
+#define MPC_MAX_CELL_PARTICLES 256
 #define MPC_MAX_BOXES 4096
 
 /* Parameters of one box.  Lengths are in units of the cell size a except a
@@ -188,7 +192,13 @@ int mpc_step(mpc_sim* s, int64_t nsteps);
  * synchronising the stream. */
 int mpc_step_profiled(mpc_sim* s, int64_t nsteps, mpc_kernel_times* acc);
 
-/* Use (1) or stop using (0) a captured hipGraph for mpc_step; default 1. */
+/* Captured hipGraphs for mpc_step: 0 = launch kernel by kernel; 1 = replay
+ * a graph of one step per step (the default); K in 2..1000 = also capture K
+ * consecutive steps in one graph, so that mpc_step(n) is floor(n / K)
+ * launches of that graph plus one-step replays for the rest.  Results do
+ * not depend on this choice.  A new K drops the captured graphs (they are
+ * captured again at the next mpc_step; synchronises).  Errors: MPC_EINVAL
+ * (enable outside 0..1000), MPC_EHIP. */
 int mpc_set_graph(mpc_sim* s, int32_t enable);
 
 /* Wait for the stream; report sticky kernel errors (MPC_ESTATE, MPC_ERANGE). */
@@ -214,6 +224,19 @@ int mpc_set_step(mpc_sim* s, uint64_t step);
  * stored.  Both synchronise. */
 int mpc_set_state(mpc_sim* s, int32_t box, const double* x, const double* v, int64_t n);
 int mpc_get_state(mpc_sim* s, int32_t box, double* x, double* v, int64_t n);
+
+/* State of selected particles of one box, for sampling a box too large to
+ * copy whole: for k in [0, m), x[k], x[m + k], x[2m + k] and v[k], v[m + k],
+ * v[2m + k] receive the position and velocity of the particle with logical
+ * index idx[k] -- the index at which mpc_get_state would return it -- with
+ * the same conversion as mpc_get_state (exact FP64 of what is stored, times
+ * a).  idx entries lie in [0, n) and may repeat; x and v hold 3m doubles
+ * each, caller-owned.  Takes temporary device memory (4 n + 52 m bytes) for
+ * the duration of the call.  Synchronises.  Errors: MPC_EINVAL (index
+ * outside the box, NULL pointer with m > 0), MPC_EHIP, and sticky kernel
+ * errors (MPC_ESTATE, MPC_ERANGE). */
+int mpc_get_particles(mpc_sim* s, int32_t box, const int64_t* idx, int64_t m, double* x,
+                      double* v);
 
 /* Binning of the last completed step of one box (synchronises):
  *   offset[ncell+1]: exclusive prefix of particles per cell;
@@ -250,6 +273,20 @@ int mpc_get_tiling(mpc_sim* s, int32_t* tile_cells, int32_t* grid, int32_t* yblo
 
 /* Release the handle (not the workspace or the stream).  Synchronises. */
 int mpc_destroy(mpc_sim* s);
+
+/* Bandwidth probes (measurement only; no MPC state): plain streaming kernels
+ * that give the HBM bandwidth a kernel attains on this device, the
+ * reference beside which the MPC kernels' byte rates are reported.
+ * mpc_probe_copy copies `bytes` from src to dst (device pointers, 16-byte
+ * aligned, bytes a multiple of 16, non-overlapping): every byte read and
+ * written once.  mpc_probe_read reads `bytes` from src once and writes one
+ * 32-bit XOR fold per thread to out (device memory of at least
+ * grid * 256 * 4 bytes, out_bytes).  grid: workgroups of 256 threads,
+ * 0 = 8 per compute unit.  Both only enqueue on hip_stream (NULL = default
+ * stream).  Errors: MPC_EINVAL (alignment, size, out too small), MPC_EHIP. */
+int mpc_probe_copy(void* dst, const void* src, size_t bytes, int32_t grid, void* hip_stream);
+int mpc_probe_read(const void* src, size_t bytes, void* out, size_t out_bytes, int32_t grid,
+                   void* hip_stream);
 
 const char* mpc_strerror(int code);
 const char* mpc_last_error(mpc_sim* s);

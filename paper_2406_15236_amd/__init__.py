@@ -21,7 +21,7 @@ from .build import LIB
 FP64, FP32, SPLIT32 = 0, 1, 2
 MBS, WALLS_Z, AMC, FIXED_SUMS, SLIP = 1, 2, 4, 8, 16
 FORMS = {"fp64": FP64, "fp32": FP32, "split": SPLIT32}
-MAX_CELL_PARTICLES = 1024
+MAX_CELL_PARTICLES = 256
 
 OK, EINVAL, ENOSPACE, ERANGE, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
 
@@ -56,9 +56,10 @@ class KernelTimes(C.Structure):
 SYMBOLS = ["mpc_workspace_bytes", "mpc_create", "mpc_init_state", "mpc_step",
            "mpc_step_profiled", "mpc_set_graph", "mpc_sync", "mpc_observables",
            "mpc_box_info", "mpc_get_step", "mpc_set_step", "mpc_set_state", "mpc_get_state",
+           "mpc_get_particles",
            "mpc_get_binning", "mpc_autotune", "mpc_set_tiling", "mpc_get_tiling", "mpc_destroy",
            "mpc_strerror",
-           "mpc_last_error"]
+           "mpc_last_error", "mpc_probe_copy", "mpc_probe_read"]
 
 _lib = None
 
@@ -88,6 +89,8 @@ def lib():
             "mpc_set_step": (C.c_int, [vp, C.c_uint64]),
             "mpc_set_state": (C.c_int, [vp, C.c_int32, f64p, f64p, C.c_int64]),
             "mpc_get_state": (C.c_int, [vp, C.c_int32, f64p, f64p, C.c_int64]),
+            "mpc_get_particles": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int64), C.c_int64,
+                                            f64p, f64p]),
             "mpc_get_binning": (C.c_int, [vp, C.c_int32, u32p, u32p, u32p]),
             "mpc_autotune": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int32),
                                        C.POINTER(C.c_int32)]),
@@ -95,6 +98,8 @@ def lib():
             "mpc_get_tiling": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
             "mpc_destroy": (C.c_int, [vp]),
+            "mpc_probe_copy": (C.c_int, [vp, vp, C.c_size_t, C.c_int32, vp]),
+            "mpc_probe_read": (C.c_int, [vp, C.c_size_t, vp, C.c_size_t, C.c_int32, vp]),
             "mpc_strerror": (C.c_char_p, [C.c_int]),
             "mpc_last_error": (C.c_char_p, [vp]),
         }
@@ -114,6 +119,17 @@ def _check(rc: int, handle=None):
             if detail:
                 msg += ": " + detail
         raise MPCError(rc, msg)
+
+
+def probe_copy(dst_ptr: int, src_ptr: int, nbytes: int, grid: int, stream_ptr: int):
+    """Enqueue the HBM copy probe (device pointers)."""
+    _check(lib().mpc_probe_copy(dst_ptr, src_ptr, nbytes, grid, stream_ptr))
+
+
+def probe_read(src_ptr: int, nbytes: int, out_ptr: int, out_bytes: int, grid: int,
+               stream_ptr: int):
+    """Enqueue the HBM read probe (device pointers)."""
+    _check(lib().mpc_probe_read(src_ptr, nbytes, out_ptr, out_bytes, grid, stream_ptr))
 
 
 def make_params(box: dict, form="fp64", flags: int | None = None, reorder_every: int = 0,
@@ -232,8 +248,10 @@ class Sim:
         self._c(lib().mpc_step_profiled(self.h, nsteps, C.byref(acc)))
         return acc
 
-    def set_graph(self, enable: bool):
-        self._c(lib().mpc_set_graph(self.h, int(bool(enable))))
+    def set_graph(self, enable):
+        """False/0: kernel by kernel; True/1: one-step graph; K > 1: also a
+        graph of K consecutive steps."""
+        self._c(lib().mpc_set_graph(self.h, int(enable)))
 
     def sync(self):
         self._c(lib().mpc_sync(self.h))
@@ -263,6 +281,16 @@ class Sim:
         x = np.empty((3, n))
         v = np.empty((3, n))
         self._c(lib().mpc_get_state(self.h, box, _f64(x), _f64(v), n))
+        return x, v
+
+    def get_particles(self, idx, box: int = 0):
+        """(x, v), each (3, m) FP64: the particles with logical indices idx."""
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        m = idx.size
+        x = np.empty((3, m))
+        v = np.empty((3, m))
+        self._c(lib().mpc_get_particles(self.h, box, idx.ctypes.data_as(C.POINTER(C.c_int64)), m,
+                                        _f64(x), _f64(v)))
         return x, v
 
     def get_binning(self, box: int = 0):

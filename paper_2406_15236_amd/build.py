@@ -9,6 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmpc355.so")
 SOURCES = [os.path.join(HERE, "csrc", "mpc_kernels.hip"),
+           os.path.join(HERE, "csrc", "mpc_probe.hip"),
            os.path.join(HERE, "csrc", "mpc_capi.cpp")]
 
 # -ffp-contract=off: every written floating-point operation is one IEEE

@@ -19,6 +19,8 @@ namespace {
 
 constexpr uint64_t kMaxIndex = 0x7fffffffull;  // particle and cell indices stay below 2^31
 constexpr int kMinTileCells = 4;
+constexpr int32_t kMaxGraphSteps = 1000;  // steps captured in one graph
+static_assert(MPC_MAX_CELL_PARTICLES == kTileCap, "the ABI's cell limit is one collide pass");
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -194,8 +196,10 @@ struct mpc_sim {
   bool keys_valid = false;
   bool have_binning = false;
   bool use_graph = true;
+  int32_t graph_steps = 1;         // steps per replay of the chunk graph
   bool graph_ready = false;
-  hipGraphExec_t gexec = nullptr;
+  hipGraphExec_t gexec = nullptr;  // one step
+  hipGraphExec_t gexec_k = nullptr;  // graph_steps steps (graph_steps > 1)
   hipStream_t capture_stream = nullptr;
   int tile_override = 0, grid_override = 0, yblock = 8;
   int num_cu = 256, occupancy = 4;
@@ -300,7 +304,8 @@ int check_sticky(mpc_sim* s) {
     return MPC_ESTATE;
   }
   if (c.err & kErrCellOverflow) {
-    s->err = "a cell held more than MPC_MAX_CELL_PARTICLES particles";
+    s->err = "a collision cell held more than MPC_MAX_CELL_PARTICLES (256) particles; "
+             "it was streamed but not collided";
     return MPC_ERANGE;
   }
   if (c.err & kErrFixRange) {
@@ -340,25 +345,40 @@ int drop_graph(mpc_sim* s) {
     HIPCHK(s, hipGraphExecDestroy(s->gexec));
     s->gexec = nullptr;
   }
+  if (s->gexec_k) {
+    HIPCHK(s, hipGraphExecDestroy(s->gexec_k));
+    s->gexec_k = nullptr;
+  }
   s->graph_ready = false;
   return MPC_OK;
 }
 
-int capture_graph(mpc_sim* s) {
-  if (s->graph_ready) return MPC_OK;
+// One executable graph of `steps` consecutive steps (every step reads the
+// step counter and the state buffer index from device memory, so one graph
+// serves every replay).
+int capture_steps(mpc_sim* s, int32_t steps, hipGraphExec_t* out) {
   if (!s->capture_stream) HIPCHK(s, hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking));
   hipGraph_t g = nullptr;
   HIPCHK(s, hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal));
-  hipError_t e = enqueue_step(s, s->capture_stream);
+  hipError_t e = hipSuccess;
+  for (int32_t k = 0; k < steps && e == hipSuccess; ++k) e = enqueue_step(s, s->capture_stream);
   hipError_t e2 = hipStreamEndCapture(s->capture_stream, &g);
   if (e != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
     return hip_fail(s, e, "capture step");
   }
   if (e2 != hipSuccess) return hip_fail(s, e2, "hipStreamEndCapture");
-  e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return hip_fail(s, e, "hipGraphInstantiate");
+  return MPC_OK;
+}
+
+int capture_graph(mpc_sim* s) {
+  if (s->graph_ready) return MPC_OK;
+  int rc = capture_steps(s, 1, &s->gexec);
+  if (!rc && s->graph_steps > 1) rc = capture_steps(s, s->graph_steps, &s->gexec_k);
+  if (rc) return rc;
   s->graph_ready = true;
   return MPC_OK;
 }
@@ -590,7 +610,13 @@ int mpc_destroy(mpc_sim* s) {
 }
 
 int mpc_set_graph(mpc_sim* s, int32_t enable) {
-  if (!s) return MPC_EINVAL;
+  if (!s || enable < 0 || enable > kMaxGraphSteps) return MPC_EINVAL;
+  if (enable >= 1 && enable != s->graph_steps) {
+    HIPCHK(s, hipStreamSynchronize(s->L.stream));
+    int rc = drop_graph(s);
+    if (rc) return rc;
+    s->graph_steps = enable;
+  }
   s->use_graph = enable != 0;
   return MPC_OK;
 }
@@ -627,7 +653,11 @@ int mpc_step(mpc_sim* s, int64_t nsteps) {
   if (rc) return rc;
   if (s->use_graph) {
     if ((rc = capture_graph(s))) return rc;
-    for (int64_t k = 0; k < nsteps; ++k) HIPCHK(s, hipGraphLaunch(s->gexec, s->L.stream));
+    int64_t k = 0;
+    if (s->gexec_k)
+      for (; k + s->graph_steps <= nsteps; k += s->graph_steps)
+        HIPCHK(s, hipGraphLaunch(s->gexec_k, s->L.stream));
+    for (; k < nsteps; ++k) HIPCHK(s, hipGraphLaunch(s->gexec, s->L.stream));
   } else {
     for (int64_t k = 0; k < nsteps; ++k) HIPCHK(s, enqueue_step(s, s->L.stream));
   }
@@ -894,6 +924,77 @@ int mpc_get_state(mpc_sim* s, int32_t box, double* x, double* v, int64_t n) {
       } else {
         for (int64_t i = 0; i < n; ++i) dst[lid[i]] = (double)buf[i] * a;
       }
+    }
+  }
+  return MPC_OK;
+}
+
+int mpc_get_particles(mpc_sim* s, int32_t box, const int64_t* idx, int64_t m, double* x,
+                      double* v) {
+  if (!s || box < 0 || box >= (int32_t)s->boxes.size() || m < 0) return MPC_EINVAL;
+  if (m > 0 && (!idx || !x || !v)) return MPC_EINVAL;
+  const BoxDev& B = s->boxes[box];
+  if (m > (int64_t)kMaxIndex) {
+    s->err = "more than 2^31 - 1 particles requested";
+    return MPC_EINVAL;
+  }
+  std::vector<uint32_t> lidx((size_t)m);
+  for (int64_t k = 0; k < m; ++k) {
+    if (idx[k] < 0 || idx[k] >= (int64_t)B.np) {
+      s->err = "particle index outside the box";
+      return MPC_EINVAL;
+    }
+    lidx[k] = (uint32_t)idx[k];
+  }
+  int rc = mpc_sync(s);
+  if (rc || m == 0) return rc;
+  const StatePtrs& S = s->dev.S[s->cur];
+  uint32_t* dinv = nullptr;
+  uint32_t* dl = nullptr;
+  double* dout = nullptr;
+  std::vector<double> out(6 * (size_t)m);
+  hipError_t e = hipSuccess;
+  const char* where = "";
+  do {
+    if (S.id) {
+      where = "hipMalloc (inverse index)";
+      if ((e = hipMalloc(&dinv, sizeof(uint32_t) * (size_t)B.np)) != hipSuccess) break;
+      where = "hipMemsetAsync";
+      if ((e = hipMemsetAsync(dinv, 0xff, sizeof(uint32_t) * (size_t)B.np, s->L.stream)) !=
+          hipSuccess)
+        break;
+    }
+    where = "hipMalloc (sample)";
+    if ((e = hipMalloc(&dl, sizeof(uint32_t) * (size_t)m)) != hipSuccess) break;
+    if ((e = hipMalloc(&dout, sizeof(double) * 6 * (size_t)m)) != hipSuccess) break;
+    where = "copy of the sample indices";
+    if ((e = hipMemcpyAsync(dl, lidx.data(), sizeof(uint32_t) * (size_t)m,
+                            hipMemcpyHostToDevice, s->L.stream)) != hipSuccess)
+      break;
+    where = "gather kernels";
+    if ((e = launch_gather_particles(s->dev, s->L, S, dinv, B.pbase, B.np, dl, (uint32_t)m,
+                                     dout)) != hipSuccess)
+      break;
+    where = "copy of the sample";
+    if ((e = hipMemcpyAsync(out.data(), dout, sizeof(double) * 6 * (size_t)m,
+                            hipMemcpyDeviceToHost, s->L.stream)) != hipSuccess)
+      break;
+    where = "hipStreamSynchronize";
+    e = hipStreamSynchronize(s->L.stream);
+  } while (false);
+  if (dinv) (void)hipFree(dinv);
+  if (dl) (void)hipFree(dl);
+  if (dout) (void)hipFree(dout);
+  if (e != hipSuccess) return hip_fail(s, e, where);
+  const double a = s->params[box].a;
+  for (int64_t k = 0; k < m; ++k) {
+    if (isnan(out[k])) {
+      s->err = "logical particle indices are not a permutation";
+      return MPC_ESTATE;
+    }
+    for (int c = 0; c < 3; ++c) {
+      x[c * m + k] = out[(size_t)c * m + k] * a;
+      v[c * m + k] = out[(size_t)(3 + c) * m + k] * a;
     }
   }
   return MPC_OK;

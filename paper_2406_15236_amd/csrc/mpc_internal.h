@@ -146,6 +146,11 @@ hipError_t launch_init_state(const Dev& d, const Launch& l, uint64_t seed);
 hipError_t launch_obs_pass1(const Dev& d, const Launch& l);
 hipError_t launch_obs_pass2(const Dev& d, const Launch& l, const double* vmean_dev);
 hipError_t launch_remove_mean(const Dev& d, const Launch& l, const double* vmean_dev);
+// inv: np entries filled with 0xffffffff by the caller (null: slots are the
+// logical order); lidx: box-local logical indices; out: [6][m] FP64
+hipError_t launch_gather_particles(const Dev& d, const Launch& l, const StatePtrs& S,
+                                  uint32_t* inv, uint32_t pbase, uint32_t np,
+                                  const uint32_t* lidx, uint32_t m, double* out);
 hipError_t launch_canon_perm(const Dev& d, const Launch& l, const uint32_t* ids);
 hipError_t collide_occupancy(const Launch& l, int* blocks_per_cu);  // flags of l only
 

@@ -2119,6 +2119,56 @@ __global__ void k_canon_perm(uint32_t* __restrict__ perm, const uint32_t* __rest
 }
 
 // ---------------------------------------------------------------------------
+// Sampled state: the inverse of one box's logical-index array, then a gather
+// of selected logical particles as FP64 in cell units (the split form's
+// cell + offset is exact in FP64).  A logical index with no stored slot
+// yields NaN.
+// ---------------------------------------------------------------------------
+__global__ void k_invert_ids(const uint32_t* __restrict__ id, uint32_t pbase, uint32_t np,
+                             uint32_t* __restrict__ inv) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < np; q += stride) {
+    const uint32_t j = pbase + (uint32_t)q;
+    const uint32_t l = id[j] - pbase;
+    if (l < np) inv[l] = j;
+  }
+}
+
+template <int F>
+__global__ __launch_bounds__(kThreads) void k_gather_particles(StatePtrs S,
+                                                                const uint32_t* __restrict__ inv,
+                                                                uint32_t pbase, uint32_t np,
+                                                                const uint32_t* __restrict__ lidx,
+                                                                uint32_t m, double* __restrict__ out) {
+  const uint32_t k = blockIdx.x * kThreads + threadIdx.x;
+  if (k >= m) return;
+  const uint32_t l = lidx[k];
+  uint32_t j = 0xffffffffu;
+  if (l < np) j = inv ? inv[l] : pbase + l;
+  double r[6];
+  if (j == 0xffffffffu || j - pbase >= np) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) r[c] = __builtin_nan("");
+  } else if constexpr (F == kFormF64) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      r[c] = ((const double*)S.a[c])[j];
+      r[3 + c] = ((const double*)S.b[c])[j];
+    }
+  } else {
+    int ci[3] = {0, 0, 0};
+    if constexpr (F == kFormSplit) split_decode(S.cell[j], ci);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      r[c] = (double)ci[c] + (double)((const float*)S.a[c])[j];
+      r[3 + c] = (double)((const float*)S.b[c])[j];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) out[(uint64_t)c * m + k] = r[c];
+}
+
+// ---------------------------------------------------------------------------
 // Device init: positions uniform, velocities normal (INIT streams keyed by
 // the init seed; counter {draw, particle, box, tag}).
 // ---------------------------------------------------------------------------
@@ -2360,6 +2410,22 @@ hipError_t launch_canon_perm(const Dev& d, const Launch& l, const uint32_t* ids)
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_canon_perm, dim3((uint32_t)blocks), dim3(kThreads), 0, l.stream, d.perm,
                      d.offset, l.ctot, (uint32_t)l.ntot, ids);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_particles(const Dev& d, const Launch& l, const StatePtrs& S,
+                                  uint32_t* inv, uint32_t pbase, uint32_t np,
+                                  const uint32_t* lidx, uint32_t m, double* out) {
+  if (m == 0 || np == 0) return hipSuccess;
+  (void)d;
+  if (inv) {
+    uint64_t blocks = ((uint64_t)np + kThreads - 1) / kThreads;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_invert_ids, dim3((uint32_t)blocks), dim3(kThreads), 0, l.stream, S.id,
+                       pbase, np, inv);
+  }
+  MPC_FORM_DISPATCH(l.form, k_gather_particles, dim3((m + kThreads - 1) / kThreads),
+                    dim3(kThreads), 0, l.stream, S, inv, pbase, np, lidx, m, out);
   return hipGetLastError();
 }
 

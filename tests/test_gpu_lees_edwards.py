@@ -109,6 +109,7 @@ def test_lees_edwards_reduced_precision_one_step(mpc, form):
     np.testing.assert_array_equal(kg, ko)
     po, oo = orc.sort(ko, p.ncells)
     np.testing.assert_array_equal(og, oo)
+    np.testing.assert_array_equal(pg, po)
     vo = orc.collide(p, t0, vs, po, oo, x=x1)
     e = rel_err(v1, vo, box)
     print(f"le {form}: max e = {e.max():.3e}")
@@ -245,6 +246,7 @@ def test_batched_boxes_with_different_boundary_velocities(mpc, kind):
                        le_u=b["le_u"], uwall=b.get("uwall", 0.0), g=b["g"])
         xo, vo, ko, po, oo = orc.step(p, t0, x, v, binning=True)
         np.testing.assert_array_equal(bins[i][0], ko)
+        np.testing.assert_array_equal(bins[i][1], po)
         np.testing.assert_array_equal(bins[i][2], oo)
         np.testing.assert_array_equal(outs[i][0], xo)
         e = rel_err(outs[i][1], vo, b)

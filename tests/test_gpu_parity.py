@@ -220,16 +220,19 @@ def test_batched_parity(mpc):
 
 
 def test_graph_and_direct_launches_agree(mpc):
+    """Kernel-by-kernel launches, one-step graphs and graphs of 4 steps (two
+    replays plus one single step for 9 steps) give identical results."""
     box = box_of((10, 12, 9), mbs=True, seed=3)
     x, v = synth.box_state(box["L"], seed=2)
     res = []
-    for graph in (True, False):
+    for graph in (1, 0, 4):
         with mpc.Sim(box, form="fp64", reorder_every=4, graph=graph) as sim:
             sim.set_state(x, v)
             sim.step(9)
             res.append(sim.get_state())
-    np.testing.assert_array_equal(res[0][0], res[1][0])
-    np.testing.assert_array_equal(res[0][1], res[1][1])
+    for r in res[1:]:
+        np.testing.assert_array_equal(res[0][0], r[0])
+        np.testing.assert_array_equal(res[0][1], r[1])
 
 
 def test_autotune_keeps_results(mpc):
@@ -352,3 +355,86 @@ def test_dense_cells_split_tile_passes(mpc):
     xo, vo = orc.step(oparams(box), 0, x, v, reorder=True)
     np.testing.assert_array_equal(xg, xo)
     assert rel_err(vg, vo, box).max() <= 1e-12
+
+
+def crowd_state(box, ncrowd, seed):
+    """A dilute uniform state in which the first ncrowd particles stream to
+    the centre (3.5, 3.5, 3.5) of cell (3, 3, 3) in this step: whatever the
+    step's shift in [-1/2, 1/2), they share one collision cell."""
+    x, v = synth.box_state(box["L"], density=box["density"], seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    vc = rng.normal(0.0, 1.0, size=(3, ncrowd))
+    x[:, :ncrowd] = 3.5 - box["h"] * vc
+    v[:, :ncrowd] = vc
+    return x, v
+
+
+def test_cell_at_capacity_collides(mpc):
+    """A collision cell holding 250 particles (up to MAX_CELL_PARTICLES, one
+    on-chip pass) collides at parity with the oracle."""
+    assert mpc.MAX_CELL_PARTICLES == 256
+    box = box_of((8, 8, 8), density=300 / 512, seed=12, mbs=True)
+    x, v = crowd_state(box, 250, seed=31)
+    with mpc.Sim(box, form="fp64", reorder_every=1) as sim:
+        sim.set_state(x, v)
+        sim.step(1)
+        xg, vg = sim.get_state()
+    xo, vo, ko, po, oo = orc.step(oparams(box), 0, x, v, reorder=True, binning=True)
+    fullest = int(np.diff(oo.astype(np.int64)).max())
+    print(f"fullest cell: {fullest} particles", flush=True)
+    assert 250 <= fullest <= mpc.MAX_CELL_PARTICLES
+    np.testing.assert_array_equal(xg, xo)
+    e = rel_err(vg, vo, box)
+    report("250-particle cell", e)
+    assert e.max() <= 1e-12
+
+
+def test_cell_above_capacity_is_reported(mpc):
+    """A collision cell holding more than MAX_CELL_PARTICLES particles is not
+    collided; the next synchronising call returns ERANGE and says why."""
+    box = box_of((8, 8, 8), density=350 / 512, seed=12)
+    x, v = crowd_state(box, 300, seed=33)
+    with mpc.Sim(box, form="fp64", reorder_every=0) as sim:
+        sim.set_state(x, v)
+        sim.step(1)
+        with pytest.raises(mpc.MPCError) as e:
+            sim.sync()
+        assert e.value.code == mpc.ERANGE
+        assert "256" in str(e.value) and "not collided" in str(e.value)
+
+
+def test_non_finite_velocity_refused(mpc):
+    box = box_of((8, 8, 8))
+    x, v = synth.box_state(box["L"], seed=1)
+    with mpc.Sim(box) as sim:
+        for bad in (np.nan, np.inf):
+            vb = v.copy()
+            vb[1, 17] = bad
+            with pytest.raises(mpc.MPCError) as e:
+                sim.set_state(x, vb)
+            assert e.value.code == mpc.EINVAL
+        xb = x.copy()
+        xb[2, 3] = np.nan
+        with pytest.raises(mpc.MPCError) as e:
+            sim.set_state(xb, v)
+        assert e.value.code == mpc.EINVAL
+
+
+def test_get_particles_matches_get_state(mpc):
+    """Sampled particles (logical indices, repeats allowed) equal the same
+    entries of the full state, in every form, after steps that reorder."""
+    box = box_of((12, 10, 9), mbs=True, seed=21)
+    x, v = synth.box_state(box["L"], seed=22)
+    rng = np.random.default_rng(5)
+    for form in ("fp64", "fp32", "split"):
+        with mpc.Sim(box, form=form, reorder_every=2) as sim:
+            sim.set_state(x, v)
+            sim.step(3)
+            xg, vg = sim.get_state()
+            idx = rng.integers(0, x.shape[1], size=777)
+            xs, vs = sim.get_particles(idx)
+            np.testing.assert_array_equal(xs, xg[:, idx])
+            np.testing.assert_array_equal(vs, vg[:, idx])
+            with pytest.raises(mpc.MPCError) as e:
+                sim.get_particles(np.array([x.shape[1]]))
+            assert e.value.code == mpc.EINVAL
