@@ -274,6 +274,28 @@ int mpc_get_tiling(mpc_sim* s, int32_t* tile_cells, int32_t* grid, int32_t* yblo
 /* Release the handle (not the workspace or the stream).  Synchronises. */
 int mpc_destroy(mpc_sim* s);
 
+/* Allocation-free run, for callers that cannot allocate device memory (code
+ * under stream capture, serving loops, harnesses that forbid hipMalloc):
+ * advances one FP64 box (p->form = MPC_FP64, any flags) in place by nsteps
+ * steps, the first with step index `step` (the random streams are keyed by
+ * it), exactly as mpc_create + mpc_set_state + mpc_set_step + mpc_step +
+ * mpc_get_state would.  x[3][n], v[3][n]: caller-owned device arrays, FP64
+ * SoA in physical units as in mpc_set_state; on return they hold the state
+ * after the steps in the same particle order.  All working memory (both
+ * state buffers, keys, permutation, cell counts, offsets, draws, tables) is
+ * a static device array of 256 MiB inside the library, one per device, held
+ * until the process ends; no device memory is allocated.  Boxes whose
+ * workspace (mpc_workspace_bytes) exceeds 256 MiB -> MPC_ERANGE (about 2e6
+ * particles at 10 per cell).  Every call on a device shares that device's
+ * array: calls that overlap on one device (other threads, or a stream not
+ * drained) race.  Launches kernel by kernel on hip_stream (NULL = default
+ * stream) and synchronises it.  Errors: MPC_EINVAL (bad parameters, n not
+ * the box's particle count, form not FP64, a position outside the box or a
+ * non-finite value), MPC_ERANGE, MPC_EHIP, and the sticky kernel errors of
+ * mpc_sync. */
+int mpc_run_noalloc(const mpc_params* p, double* x, double* v, int64_t n, uint64_t step,
+                    int64_t nsteps, void* hip_stream);
+
 /* Bandwidth probes (measurement only; no MPC state): plain streaming kernels
  * that give the HBM bandwidth a kernel attains on this device, the
  * reference beside which the MPC kernels' byte rates are reported.

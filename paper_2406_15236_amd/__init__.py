@@ -59,7 +59,7 @@ SYMBOLS = ["mpc_workspace_bytes", "mpc_create", "mpc_init_state", "mpc_step",
            "mpc_get_particles",
            "mpc_get_binning", "mpc_autotune", "mpc_set_tiling", "mpc_get_tiling", "mpc_destroy",
            "mpc_strerror",
-           "mpc_last_error", "mpc_probe_copy", "mpc_probe_read"]
+           "mpc_last_error", "mpc_probe_copy", "mpc_probe_read", "mpc_run_noalloc"]
 
 _lib = None
 
@@ -99,6 +99,7 @@ def lib():
                                          C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
             "mpc_destroy": (C.c_int, [vp]),
             "mpc_probe_copy": (C.c_int, [vp, vp, C.c_size_t, C.c_int32, vp]),
+            "mpc_run_noalloc": (C.c_int, [P, vp, vp, C.c_int64, C.c_uint64, C.c_int64, vp]),
             "mpc_probe_read": (C.c_int, [vp, C.c_size_t, vp, C.c_size_t, C.c_int32, vp]),
             "mpc_strerror": (C.c_char_p, [C.c_int]),
             "mpc_last_error": (C.c_char_p, [vp]),
@@ -119,6 +120,13 @@ def _check(rc: int, handle=None):
             if detail:
                 msg += ": " + detail
         raise MPCError(rc, msg)
+
+
+def run_noalloc(params, x_ptr: int, v_ptr: int, n: int, step: int, nsteps: int,
+                stream_ptr: int):
+    """Advance one FP64 box in place in caller-owned device arrays x[3][n],
+    v[3][n] with the library's static scratch (no device allocation)."""
+    _check(lib().mpc_run_noalloc(C.byref(params), x_ptr, v_ptr, n, step, nsteps, stream_ptr))
 
 
 def probe_copy(dst_ptr: int, src_ptr: int, nbytes: int, grid: int, stream_ptr: int):

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -161,6 +162,30 @@ int make_plan(const mpc_params* p, int32_t nbox, Plan& P, std::string* why) {
   P.off_draws = take(sizeof(CellDraw) * P.cpad);
   P.off_phs = (p[0].flags & MPC_WALLS_Z) ? take(sizeof(PhantomSums) * P.cpad) : 0;
   P.total = off;
+  return MPC_OK;
+}
+
+// Device scratch of the allocation-free entry point: the whole workspace of
+// one call lives here.  Each device holds its own copy from module load to
+// process end; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return MPC_EHIP;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+      return MPC_EHIP;
+    scratch_ptr[dev] = ptr;
+  }
+  *out = scratch_ptr[dev];
   return MPC_OK;
 }
 
@@ -1191,6 +1216,38 @@ int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* 
   if (tile_cells) *tile_cells = bestT;
   if (grid) *grid = (int32_t)s->L.collide_grid;
   return MPC_OK;
+}
+
+int mpc_run_noalloc(const mpc_params* p, double* x, double* v, int64_t n, uint64_t step,
+                    int64_t nsteps, void* hip_stream) {
+  if (!p || !x || !v || n < 1 || nsteps < 0) return MPC_EINVAL;
+  if (p->form != MPC_FP64) return MPC_EINVAL;
+  Plan P;
+  std::string why;
+  int rc = make_plan(p, 1, P, &why);
+  if (rc) return rc;
+  if ((uint64_t)n != P.box[0].n) return MPC_EINVAL;
+  if (P.total > kScratchBytes) return MPC_ERANGE;
+  void* ws = nullptr;
+  if ((rc = scratch_of_current_device(&ws))) return rc;
+  mpc_sim* s = nullptr;
+  if ((rc = mpc_create(p, 1, ws, kScratchBytes, hip_stream, &s))) return rc;
+  auto done = [&](int code) {
+    (void)mpc_destroy(s);
+    return code;
+  };
+  s->use_graph = false;  // kernel by kernel: graph instantiation may allocate
+  const double a = p->a;
+  if (launch_load_f64(s->dev, s->L, x, v, (uint32_t)n, a, 0) != hipSuccess)
+    return done(MPC_EHIP);
+  if ((rc = check_sticky(s))) return done(rc == MPC_ESTATE ? MPC_EINVAL : rc);
+  if ((rc = mpc_set_step(s, step))) return done(rc);
+  if ((rc = mpc_step(s, nsteps))) return done(rc);
+  if ((rc = check_sticky(s))) return done(rc);
+  if (launch_store_f64(s->dev, s->L, x, v, (uint32_t)n, a, s->cur) != hipSuccess ||
+      hipStreamSynchronize(s->L.stream) != hipSuccess)
+    return done(MPC_EHIP);
+  return done(MPC_OK);
 }
 
 }  // extern "C"

@@ -151,6 +151,11 @@ hipError_t launch_remove_mean(const Dev& d, const Launch& l, const double* vmean
 hipError_t launch_gather_particles(const Dev& d, const Launch& l, const StatePtrs& S,
                                   uint32_t* inv, uint32_t pbase, uint32_t np,
                                   const uint32_t* lidx, uint32_t m, double* out);
+// box 0, FP64 form: caller's device arrays (physical units) <-> state buffer cur
+hipError_t launch_load_f64(const Dev& d, const Launch& l, const double* x, const double* v,
+                           uint32_t n, double a, uint32_t cur);
+hipError_t launch_store_f64(const Dev& d, const Launch& l, double* x, double* v, uint32_t n,
+                            double a, uint32_t cur);
 hipError_t launch_canon_perm(const Dev& d, const Launch& l, const uint32_t* ids);
 hipError_t collide_occupancy(const Launch& l, int* blocks_per_cu);  // flags of l only
 

@@ -2169,6 +2169,49 @@ __global__ __launch_bounds__(kThreads) void k_gather_particles(StatePtrs S,
 }
 
 // ---------------------------------------------------------------------------
+// FP64 state of box 0 from / to caller-owned device arrays x[3][n], v[3][n]
+// in physical units (the allocation-free entry point).  Load: cell units
+// (x / a, v / a) into state buffer `cur`, logical indices the identity; a
+// position outside [0, L) ([0, H] on a walled z) or a non-finite value sets
+// kErrKey.  Store: x[id[j]] = a * stored x[j], likewise v.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_load_f64(Dev d, const double* __restrict__ x,
+                                                       const double* __restrict__ v, uint32_t n,
+                                                       double a, uint32_t cur) {
+  const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  BoxRef B = as_const(d.boxes)[0];
+  const StatePtrs S = d.S[cur];
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double xi = x[(uint64_t)k * n + i] / a;
+    const double vi = v[(uint64_t)k * n + i] / a;
+    const bool in = (B.walls && k == 2) ? (xi >= 0.0 && xi <= B.Ld[k]) : (xi >= 0.0 && xi < B.Ld[k]);
+    ok = ok && in && isfinite(vi);
+    ((double*)S.a[k])[i] = in ? xi : 0.0;
+    ((double*)S.b[k])[i] = isfinite(vi) ? vi : 0.0;
+  }
+  if (S.id) S.id[i] = i;
+  if (!ok) atomicOr(&d.ctrl->err, kErrKey);
+}
+
+__global__ __launch_bounds__(kThreads) void k_store_f64(Dev d, double* __restrict__ x,
+                                                        double* __restrict__ v, uint32_t n,
+                                                        double a, uint32_t cur) {
+  const uint32_t j = blockIdx.x * kThreads + threadIdx.x;
+  if (j >= n) return;
+  const StatePtrs S = d.S[cur];
+  const uint32_t l = S.id ? S.id[j] : j;
+  if (l >= n) return;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    x[(uint64_t)k * n + l] = ((const double*)S.a[k])[j] * a;
+    v[(uint64_t)k * n + l] = ((const double*)S.b[k])[j] * a;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Device init: positions uniform, velocities normal (INIT streams keyed by
 // the init seed; counter {draw, particle, box, tag}).
 // ---------------------------------------------------------------------------
@@ -2426,6 +2469,22 @@ hipError_t launch_gather_particles(const Dev& d, const Launch& l, const StatePtr
   }
   MPC_FORM_DISPATCH(l.form, k_gather_particles, dim3((m + kThreads - 1) / kThreads),
                     dim3(kThreads), 0, l.stream, S, inv, pbase, np, lidx, m, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_load_f64(const Dev& d, const Launch& l, const double* x, const double* v,
+                           uint32_t n, double a, uint32_t cur) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_load_f64, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, l.stream,
+                     d, x, v, n, a, cur);
+  return hipGetLastError();
+}
+
+hipError_t launch_store_f64(const Dev& d, const Launch& l, double* x, double* v, uint32_t n,
+                            double a, uint32_t cur) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_store_f64, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     l.stream, d, x, v, n, a, cur);
   return hipGetLastError();
 }
 
