@@ -251,7 +251,8 @@ int mpc_get_binning(mpc_sim* s, int32_t box, uint32_t* key, uint32_t* perm, uint
 /* Autotuner: choose the collide tiling (cells per tile, persistent grid size,
  * rows per block of the tile order) by timing trial_steps steps (1..1000) of
  * each candidate from the current state, in a coordinate search (tile size,
- * then grid, then row block).  Before every trial and at the end the state
+ * then grid, then row block, then the x-segment-major order with each row
+ * block).  Before every trial and at the end the state
  * and step counter are restored from a copy, so the random streams and all
  * later results are exactly those of an untuned handle (results do not depend
  * on the tiling).  The copy is one state buffer, in temporary device memory
@@ -262,14 +263,18 @@ int mpc_get_binning(mpc_sim* s, int32_t box, uint32_t* key, uint32_t* perm, uint
 int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* grid);
 
 /* Override the collide tiling: cells per tile (4..32, 0 = automatic),
- * persistent grid size (0 = automatic) and the number of rows per block of the
- * XCD-aware tile order (0 = automatic, 8). */
-int mpc_set_tiling(mpc_sim* s, int32_t tile_cells, int32_t grid, int32_t yblock);
+ * persistent grid size (0 = automatic), the number of rows per block of the
+ * XCD-aware tile order (0 = automatic, 8) and the order inside a block
+ * (0 = the tiles of one row after another; 1 = the same x segment of every
+ * row of the block, then the next segment).  Results do not depend on the
+ * tiling.  Errors: MPC_EINVAL (out of range), MPC_EHIP. */
+int mpc_set_tiling(mpc_sim* s, int32_t tile_cells, int32_t grid, int32_t yblock, int32_t order);
 
 /* Current collide tiling: tile_cells (0 = automatic per box), persistent grid
- * size, rows per block of the tile order, and the number of tiles. */
+ * size, rows per block of the tile order, the order inside a block, and the
+ * number of tiles.  Any pointer may be NULL. */
 int mpc_get_tiling(mpc_sim* s, int32_t* tile_cells, int32_t* grid, int32_t* yblock,
-                   int64_t* ntiles);
+                   int32_t* order, int64_t* ntiles);
 
 /* Release the handle (not the workspace or the stream).  Synchronises. */
 int mpc_destroy(mpc_sim* s);

@@ -94,9 +94,10 @@ def lib():
             "mpc_get_binning": (C.c_int, [vp, C.c_int32, u32p, u32p, u32p]),
             "mpc_autotune": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int32),
                                        C.POINTER(C.c_int32)]),
-            "mpc_set_tiling": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32]),
+            "mpc_set_tiling": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
             "mpc_get_tiling": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                         C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_int64)]),
             "mpc_destroy": (C.c_int, [vp]),
             "mpc_probe_copy": (C.c_int, [vp, vp, C.c_size_t, C.c_int32, vp]),
             "mpc_run_noalloc": (C.c_int, [P, vp, vp, C.c_int64, C.c_uint64, C.c_int64, vp]),
@@ -309,13 +310,16 @@ class Sim:
         self._c(lib().mpc_get_binning(self.h, box, _u32(key), _u32(perm), _u32(off)))
         return key, perm, off
 
-    def set_tiling(self, tile_cells: int = 0, grid: int = 0, yblock: int = 0):
-        self._c(lib().mpc_set_tiling(self.h, tile_cells, grid, yblock))
+    def set_tiling(self, tile_cells: int = 0, grid: int = 0, yblock: int = 0, order: int = 0):
+        self._c(lib().mpc_set_tiling(self.h, tile_cells, grid, yblock, order))
 
     def get_tiling(self) -> dict:
-        tc, g, yb, nt = C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_int64(0)
-        self._c(lib().mpc_get_tiling(self.h, C.byref(tc), C.byref(g), C.byref(yb), C.byref(nt)))
-        return {"tile_cells": tc.value, "grid": g.value, "yblock": yb.value, "ntiles": nt.value}
+        tc, g, yb, od, nt = (C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_int32(0),
+                             C.c_int64(0))
+        self._c(lib().mpc_get_tiling(self.h, C.byref(tc), C.byref(g), C.byref(yb), C.byref(od),
+                                     C.byref(nt)))
+        return {"tile_cells": tc.value, "grid": g.value, "yblock": yb.value, "order": od.value,
+                "ntiles": nt.value}
 
     def autotune(self, trial_steps: int = 3):
         tc, g = C.c_int32(0), C.c_int32(0)

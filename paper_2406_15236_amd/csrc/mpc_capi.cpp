@@ -227,6 +227,7 @@ struct mpc_sim {
   hipGraphExec_t gexec_k = nullptr;  // graph_steps steps (graph_steps > 1)
   hipStream_t capture_stream = nullptr;
   int tile_override = 0, grid_override = 0, yblock = 8;
+  int order = 0;  // tile order: 0 = row by row inside a block of rows, 1 = x-segment major
   int num_cu = 256, occupancy = 4;
   double* vmean = nullptr;
   std::string err;
@@ -261,7 +262,9 @@ int auto_tile_cells(double density) {
 // that the persistent grid, which hands each XCD a contiguous part of the list,
 // keeps cells that exchange particles on one XCD at the same time: each XCD
 // gets a slab of z planes, walked in blocks of `yblock` rows with z inside a
-// block, so the rows a tile reads from are in flight together.
+// block (order 0: each row's tiles in turn; order 1: one x segment of all
+// rows of the block, then the next), so the rows a tile reads from are in
+// flight together.
 void build_tiles(mpc_sim* s) {
   s->tiles.clear();
   struct Keyed {
@@ -286,9 +289,13 @@ void build_tiles(mpc_sim* s) {
           t.y0 = (uint32_t)cy;
           t.z0 = (uint32_t)cz;
           const uint64_t slab = cz * 8 / (uint64_t)B.nlz;
+          const uint64_t head = ((uint64_t)b * 8 + slab) << 12 | (cy / yb);
+          // order 0: the rows of a block one after the other; order 1: the
+          // same x segment of every row of the block, then the next segment
+          // (the rows that exchange particles are in flight together)
           const uint64_t k =
-              ((((((uint64_t)b * 8 + slab) << 12 | (cy / yb)) << 11 | cz) << 11 | cy) << 12) |
-              (cx & 0xfff);
+              s->order == 0 ? (((head << 11 | cz) << 11 | cy) << 12) | (cx & 0xfff)
+                            : (((head << 12 | (cx / (uint64_t)T)) << 11 | cz) << 11) | cy;
           keyed.push_back({k, t});
         }
       }
@@ -646,15 +653,17 @@ int mpc_set_graph(mpc_sim* s, int32_t enable) {
   return MPC_OK;
 }
 
-int mpc_set_tiling(mpc_sim* s, int32_t tile_cells, int32_t grid, int32_t yblock) {
+int mpc_set_tiling(mpc_sim* s, int32_t tile_cells, int32_t grid, int32_t yblock,
+                   int32_t order) {
   if (!s) return MPC_EINVAL;
   if (tile_cells != 0 && (tile_cells < kMinTileCells || tile_cells > kTileMaxCells))
     return MPC_EINVAL;
-  if (grid < 0 || yblock < 0 || yblock > 4096) return MPC_EINVAL;
+  if (grid < 0 || yblock < 0 || yblock > 4096 || order < 0 || order > 1) return MPC_EINVAL;
   HIPCHK(s, hipStreamSynchronize(s->L.stream));
   s->tile_override = tile_cells;
   s->grid_override = grid;
   s->yblock = yblock ? yblock : 8;
+  s->order = order;
   build_tiles(s);
   int rc = drop_graph(s);
   if (rc) return rc;
@@ -662,11 +671,12 @@ int mpc_set_tiling(mpc_sim* s, int32_t tile_cells, int32_t grid, int32_t yblock)
 }
 
 int mpc_get_tiling(mpc_sim* s, int32_t* tile_cells, int32_t* grid, int32_t* yblock,
-                   int64_t* ntiles) {
+                   int32_t* order, int64_t* ntiles) {
   if (!s) return MPC_EINVAL;
   if (tile_cells) *tile_cells = s->tile_override;
   if (grid) *grid = (int32_t)s->L.collide_grid;
   if (yblock) *yblock = s->yblock;
+  if (order) *order = s->order;
   if (ntiles) *ntiles = (int64_t)s->L.ntiles;
   return MPC_OK;
 }
@@ -1097,7 +1107,7 @@ int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* 
   hipStream_t st = s->L.stream;
   const uint64_t step0 = s->step;
   const uint32_t cur0 = s->cur;
-  const int T0 = s->tile_override, g0 = s->grid_override, y0 = s->yblock;
+  const int T0 = s->tile_override, g0 = s->grid_override, y0 = s->yblock, o0 = s->order;
   // the arrays of the current state buffer, backed up on the device (or in
   // host memory if the device has no room) and restored before every trial
   std::vector<std::pair<void*, size_t>> arrs;
@@ -1155,8 +1165,8 @@ int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* 
   // one trial: set the tiling, one untimed step (binning prologue), then
   // trial_steps timed steps; returns milliseconds per step
   hipEvent_t ev[2] = {nullptr, nullptr};
-  auto trial = [&](int T, int g, int yb, double* ms) -> int {
-    int r = mpc_set_tiling(s, T, g, yb);
+  auto trial = [&](int T, int g, int yb, int ord, double* ms) -> int {
+    int r = mpc_set_tiling(s, T, g, yb, ord);
     if (r) return r;
     if ((r = restore())) return r;
     if ((r = ensure_keys(s))) return r;
@@ -1174,7 +1184,7 @@ int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* 
   };
   rc = MPC_OK;
   if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) rc = MPC_EHIP;
-  int bestT = T0, bestG = g0, bestY = y0;
+  int bestT = T0, bestG = g0, bestY = y0, bestO = o0;
   double best = 1e300;
   // coordinate search: tile size, then the persistent grid, then the row block
   const int Ts[] = {0, 8, 12, 16, 20, 22, 24, 28, 32};
@@ -1186,25 +1196,32 @@ int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* 
   const int ys[] = {8, 4, 16};
   for (int T : Ts) {
     double ms;
-    if (rc || (rc = trial(T, 0, 8, &ms))) break;
-    if (ms < best) best = ms, bestT = T, bestG = 0, bestY = 8;
+    if (rc || (rc = trial(T, 0, 8, 0, &ms))) break;
+    if (ms < best) best = ms, bestT = T, bestG = 0, bestY = 8, bestO = 0;
   }
   for (int g : gs) {
     double ms;
     if (rc || g == 0) continue;
-    if ((rc = trial(bestT, (g + 7) / 8 * 8, bestY, &ms))) break;
+    if ((rc = trial(bestT, (g + 7) / 8 * 8, bestY, 0, &ms))) break;
     if (ms < best) best = ms, bestG = (g + 7) / 8 * 8;
   }
   for (int yb : ys) {
     double ms;
     if (rc || yb == 8) continue;
-    if ((rc = trial(bestT, bestG, yb, &ms))) break;
+    if ((rc = trial(bestT, bestG, yb, 0, &ms))) break;
     if (ms < best) best = ms, bestY = yb;
+  }
+  // then the x-segment-major order with each row block
+  for (int yb : ys) {
+    double ms;
+    if (rc) break;
+    if ((rc = trial(bestT, bestG, yb, 1, &ms))) break;
+    if (ms < best) best = ms, bestY = yb, bestO = 1;
   }
   for (hipEvent_t x : ev)
     if (x) (void)hipEventDestroy(x);
   const std::string why = s->err;
-  int rc2 = mpc_set_tiling(s, rc ? T0 : bestT, rc ? g0 : bestG, rc ? y0 : bestY);
+  int rc2 = mpc_set_tiling(s, rc ? T0 : bestT, rc ? g0 : bestG, rc ? y0 : bestY, rc ? o0 : bestO);
   int rc3 = restore();
   release();
   if (rc) {

@@ -439,6 +439,38 @@ __device__ __forceinline__ bool coords_of(const int (&ci)[3], const double (&xf)
   return ok;
 }
 
+// Split form: c_k = cell_k + floor(o_k + s_k) with the sum in FP32, which
+// gives the exact floor: o is an FP32 offset in [0, 1) and s lies on the
+// 2^-24 grid in [-1/2, 1/2), so o + s is exact whenever it is below 1 or near
+// 0 (Sterbenz), and a sum of at least 1 stays below 2.
+template <bool W>
+__device__ __forceinline__ bool coords_split(const int (&ci)[3], const float (&o)[3],
+                                             const double (&s)[3], BoxRef B, int (&c)[3],
+                                             uint32_t& err) {
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float y = o[k] + (float)s[k];
+    const bool in = y >= -2.0f && y < 2.0f;
+    ok = ok && in;
+    c[k] = ci[k] + (int)floorf(in ? y : 0.0f);
+  }
+  c[0] = wrap1(c[0], B.L[0]);
+  c[1] = wrap1(c[1], B.L[1]);
+  if (W) {
+    c[2] += 1;
+  } else {
+    c[2] = wrap1(c[2], B.L[2]);
+  }
+  ok = ok && (unsigned)c[0] < (unsigned)B.L[0] && (unsigned)c[1] < (unsigned)B.L[1] &&
+       (unsigned)c[2] < (unsigned)B.nlz;
+  if (__builtin_expect(!ok, 0)) {
+    err |= kErrKey;
+    c[0] = c[1] = c[2] = 0;
+  }
+  return ok;
+}
+
 __device__ __forceinline__ uint32_t linear_key(const int (&c)[3], BoxRef B) {
   return (uint32_t)((c[2] * B.L[1] + c[1]) * B.L[0] + c[0]);
 }
@@ -625,20 +657,24 @@ struct Form<kFormSplit> {
     stream_split<W>(p.cell, p.o, v.v, B, dle, le);
   }
   template <bool W>
-  __device__ static uint32_t key(const P& p, const double (&s)[3], BoxRef B,
-                                 uint32_t& err, double dle, bool le) {
-    int ci[3];
-    split_decode(p.cell, ci);
-    const double xf[3] = {(double)p.o[0], (double)p.o[1], (double)p.o[2]};
-    return key_of<W>(ci, xf, s, B, err, dle, le);
-  }
-  template <bool W>
   __device__ static void coords(const P& p, const double (&s)[3], BoxRef B, int (&c)[3],
                                 uint32_t& err, double dle, bool le) {
     int ci[3];
     split_decode(p.cell, ci);
+    if (!le) {
+      coords_split<W>(ci, p.o, s, B, c, err);
+      return;
+    }
+    // Lees-Edwards: the image offset is applied in FP64
     const double xf[3] = {(double)p.o[0], (double)p.o[1], (double)p.o[2]};
     coords_of<W>(ci, xf, s, B, c, err, dle, le);
+  }
+  template <bool W>
+  __device__ static uint32_t key(const P& p, const double (&s)[3], BoxRef B,
+                                 uint32_t& err, double dle, bool le) {
+    int c[3];
+    coords<W>(p, s, B, c, err, dle, le);
+    return linear_key(c, B);
   }
   __device__ static int le_side(const P& p, double sz, BoxRef B) {
     int ci[3];

@@ -261,6 +261,29 @@ def test_autotune_keeps_results(mpc):
     np.testing.assert_array_equal(oa, ob)
 
 
+@pytest.mark.parametrize("form", ["fp64", "split"])
+def test_tile_order_and_size_keep_results(mpc, form):
+    """Tile size, row block and tile order (row by row, or one x segment of
+    every row of a block at a time) change only the schedule: results are
+    bit-identical, including a tiling change between steps."""
+    box = box_of((37, 21, 19), mbs=True, seed=13)
+    x, v = synth.box_state(box["L"], seed=14)
+    res = []
+    for tiling in [(0, 0, 0, 0), (12, 0, 4, 1), (32, 1024, 16, 1), (8, 0, 8, 0)]:
+        with mpc.Sim(box, form=form, reorder_every=3) as sim:
+            sim.set_tiling(*tiling)
+            sim.set_state(x, v)
+            sim.step(3)
+            sim.set_tiling(24, 0, 8, 1 - tiling[3])
+            sim.step(2)
+            res.append((sim.get_state(), sim.get_binning()))
+    for (xs, vs), (k, p, o) in res[1:]:
+        np.testing.assert_array_equal(xs, res[0][0][0])
+        np.testing.assert_array_equal(vs, res[0][0][1])
+        np.testing.assert_array_equal(p, res[0][1][1])
+        np.testing.assert_array_equal(o, res[0][1][2])
+
+
 def test_deterministic(mpc):
     box = box_of((12, 12, 12), mbs=True, seed=8)
     x, v = synth.box_state(box["L"], seed=4)
