@@ -133,31 +133,41 @@ def form_entry(workload: str, form: str, n: int, steps: int, wall: float, kt, ex
 
 
 def hbm_probe(mpc, torch, gib: float = 4.0, reps: int = 5):
-    """The library's plain copy and read kernels on a `gib` GiB buffer: best
-    of `reps` launches each, timed with HIP events on torch's stream."""
+    """The library's plain copy and read kernels on a `gib` GiB buffer, over
+    several grid sizes: best of `reps` launches each, timed with HIP events on
+    torch's stream; the fastest grid is reported."""
     nb = int(gib * 2 ** 30)
     src = torch.empty(nb, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     src.fill_(1)
     st = torch.cuda.current_stream().cuda_stream
-    out = torch.empty(8 * 256 * 256 * 4, dtype=torch.uint8, device="cuda")
+    grids = (1024, 2048, 4096, 8192, 16384)
+    out = torch.empty(max(grids) * 256 * 4, dtype=torch.uint8, device="cuda")
     res = {"bytes": nb}
     for name in ("copy", "read"):
-        best = None
-        for r in range(reps + 1):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            if name == "copy":
-                mpc.probe_copy(dst.data_ptr(), src.data_ptr(), nb, 0, st)
-            else:
-                mpc.probe_read(src.data_ptr(), nb, out.data_ptr(), out.numel(), 0, st)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
-            if r and (best is None or ms < best):   # the first launch is a warm-up
-                best = ms
+        best, best_grid, per_grid = None, None, {}
+        for grid in grids:
+            g_best = None
+            for r in range(reps + 1):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                if name == "copy":
+                    mpc.probe_copy(dst.data_ptr(), src.data_ptr(), nb, grid, st)
+                else:
+                    mpc.probe_read(src.data_ptr(), nb, out.data_ptr(), out.numel(), grid, st)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1)
+                if r and (g_best is None or ms < g_best):   # the first launch is a warm-up
+                    g_best = ms
+            per_grid[grid] = g_best
+            if best is None or g_best < best:
+                best, best_grid = g_best, grid
         moved = 2 * nb if name == "copy" else nb
-        res[name] = {"ms": best, "GBs": moved / (best * 1e-3) / 1e9}
+        res[name] = {"ms": best, "GBs": moved / (best * 1e-3) / 1e9, "grid": best_grid,
+                     "GBs_by_grid": {str(g): round(moved / (t * 1e-3) / 1e9, 1)
+                                     for g, t in per_grid.items()}}
     del src, dst, out
     torch.cuda.empty_cache()
     log(f"[hbm probe] copy {res['copy']['GBs']:.0f} GB/s, read {res['read']['GBs']:.0f} GB/s")
@@ -408,6 +418,8 @@ def main():
                     {"particles": nb})
                 _, _, kb, _, _ = run_box(mpc, torch, boxes, fm, 0, 20, 5)
                 forms[form]["collide_ms_profiled"] = kb.collide_ms / max(1, kb.collide_launches)
+                trb = traffic_record(fm, "C4", 0)
+                forms[form]["collide_traffic_bytes"] = trb["bytes_per_launch"] if trb else None
                 forms[form]["collide_roofline_frac_profiled"] = (
                     nb * 2 * STATE_BYTES[fm] / (forms[form]["collide_ms_profiled"] * 1e-3) / 1e9
                     / HBM_PEAK_GBS)
