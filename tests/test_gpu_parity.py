@@ -461,3 +461,52 @@ def test_get_particles_matches_get_state(mpc):
             with pytest.raises(mpc.MPCError) as e:
                 sim.get_particles(np.array([x.shape[1]]))
             assert e.value.code == mpc.EINVAL
+
+
+@pytest.mark.parametrize("form,R", [("fp64", 0), ("fp64", 5), ("fp32", 5), ("split", 0),
+                                    ("split", 5)])
+def test_checkpoint_resume(mpc, form, R):
+    """20 steps in one run equal 10 steps, a checkpoint (state in the caller's
+    order and the step counter) restored into a new handle, and 10 more steps,
+    bit for bit: the random streams are keyed by (seed, step, cell) and the
+    cell sums run in logical order, so nothing else needs saving."""
+    box = box_of((14, 11, 9), mbs=True, g=(1e-3, 0.0, 0.0), seed=19)
+    x, v = synth.box_state(box["L"], seed=20)
+    with mpc.Sim(box, form=form, reorder_every=R) as sim:
+        sim.set_state(x, v)
+        sim.step(20)
+        xa, va = sim.get_state()
+    with mpc.Sim(box, form=form, reorder_every=R) as sim:
+        sim.set_state(x, v)
+        sim.step(10)
+        xc, vc = sim.get_state()
+        tc = sim.get_step()
+    with mpc.Sim(box, form=form, reorder_every=R) as sim:
+        sim.set_state(xc, vc)
+        sim.set_step(tc)
+        sim.step(10)
+        xb, vb = sim.get_state()
+    np.testing.assert_array_equal(xa, xb)
+    np.testing.assert_array_equal(va, vb)
+
+
+def test_tuning_cache_on_device(mpc, tmp_path):
+    """The tiling cache: a miss runs the autotuner and stores its choice, a
+    hit applies it without timing runs; results are unchanged either way."""
+    from paper_2406_15236_amd import tuning
+    box = box_of((40, 36, 30), mbs=True, seed=37)
+    x, v = synth.box_state(box["L"], seed=38)
+    path = str(tmp_path / "tiles.json")
+    res = []
+    for expect_hit in (False, True):
+        with mpc.Sim(box, form="fp64", reorder_every=5) as sim:
+            sim.set_state(x, v)
+            sim.step(1)
+            t, hit = tuning.autotune_cached(sim, 2, path=path)
+            assert hit == expect_hit
+            assert sim.get_step() == 1
+            sim.step(4)
+            res.append(sim.get_state())
+            print(f"tiling {t} (hit={hit}): {sim.get_tiling()}")
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    np.testing.assert_array_equal(res[0][1], res[1][1])
