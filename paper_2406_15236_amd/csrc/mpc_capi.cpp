@@ -19,6 +19,7 @@ using namespace mpc;
 namespace {
 
 constexpr uint64_t kMaxIndex = 0x7fffffffull;  // particle and cell indices stay below 2^31
+constexpr int64_t kStateChunk = int64_t(1) << 22;  // particles per host staging chunk
 constexpr int kMinTileCells = 4;
 constexpr int32_t kMaxGraphSteps = 1000;  // steps captured in one graph
 static_assert(MPC_MAX_CELL_PARTICLES == kTileCap, "the ABI's cell limit is one collide pass");
@@ -35,11 +36,11 @@ struct Plan {
   uint64_t ntot = 0, ctot = 0, cpad = 0;
   uint32_t nscan = 0;
   uint64_t max_tiles = 0, npblocks = 0;
-  size_t state_elem_a = 0, state_elem_b = 0;  // bytes per component
+  size_t rec = 0;  // bytes per particle record
   bool split = false;
-  // byte offsets in the workspace
-  size_t off_S[2][8] = {};
-  bool ids = true;  // logical-index arrays (the stored order is free)
+  // byte offsets in the workspace: records of the two state buffers and, for
+  // FP64 and FP32, their logical-index arrays (the split record holds its id)
+  size_t off_rec[2] = {}, off_id[2] = {};
   size_t off_rank = 0, off_phs = 0;
   size_t off_key = 0, off_perm = 0, off_hist = 0, off_offset = 0, off_scan = 0, off_ctrl = 0,
          off_boxes = 0, off_tiles = 0, off_pblocks = 0, off_partials = 0, off_vmean = 0,
@@ -132,9 +133,7 @@ int make_plan(const mpc_params* p, int32_t nbox, Plan& P, std::string* why) {
   }
   const int form = p[0].form;
   P.split = form == MPC_SPLIT32;
-  P.ids = true;
-  P.state_elem_a = form == MPC_FP64 ? 8 : 4;
-  P.state_elem_b = form == MPC_FP64 ? 8 : 4;
+  P.rec = form == MPC_FP64 ? sizeof(RecF64) : (form == MPC_FP32 ? sizeof(RecF32) : sizeof(RecSplit));
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -142,10 +141,8 @@ int make_plan(const mpc_params* p, int32_t nbox, Plan& P, std::string* why) {
     return o;
   };
   for (int s = 0; s < 2; ++s) {
-    for (int k = 0; k < 3; ++k) P.off_S[s][k] = take(P.state_elem_a * P.ntot);
-    for (int k = 0; k < 3; ++k) P.off_S[s][3 + k] = take(P.state_elem_b * P.ntot);
-    P.off_S[s][6] = P.split ? take(4 * P.ntot) : 0;
-    P.off_S[s][7] = P.ids ? take(4 * P.ntot) : 0;
+    P.off_rec[s] = take(P.rec * P.ntot);
+    P.off_id[s] = P.split ? 0 : take(4 * P.ntot);
   }
   P.off_key = take(4 * P.ntot);
   P.off_perm = take(4 * P.ntot);
@@ -429,6 +426,30 @@ int copy_d2h(mpc_sim* s, const void* src_base, uint64_t elem0, std::vector<T>& d
   return MPC_OK;
 }
 
+// Logical indices of slots p0 .. p0 + out.size() - 1 of state buffer S: a copy
+// of the id array, or of the records a chunk at a time (ids inside records).
+int read_ids(mpc_sim* s, const StatePtrs& S, uint64_t p0, std::vector<uint32_t>& out) {
+  const uint64_t n = out.size();
+  if (S.id_stride == 1) {
+    HIPCHK(s, hipMemcpyAsync(out.data(), S.id + p0, sizeof(uint32_t) * n, hipMemcpyDeviceToHost,
+                             s->L.stream));
+    HIPCHK(s, hipStreamSynchronize(s->L.stream));
+    return MPC_OK;
+  }
+  const uint64_t st = S.id_stride;
+  const uint64_t w = (uint64_t)(S.id - (const uint32_t*)S.rec);  // id word inside a record
+  const uint64_t chunk = std::min<uint64_t>(n, (uint64_t)kStateChunk);
+  std::vector<uint32_t> buf((size_t)(chunk * st));
+  for (uint64_t i0 = 0; i0 < n; i0 += chunk) {
+    const uint64_t m = std::min(chunk, n - i0);
+    HIPCHK(s, hipMemcpyAsync(buf.data(), (const uint32_t*)S.rec + (p0 + i0) * st,
+                             sizeof(uint32_t) * m * st, hipMemcpyDeviceToHost, s->L.stream));
+    HIPCHK(s, hipStreamSynchronize(s->L.stream));
+    for (uint64_t i = 0; i < m; ++i) out[i0 + i] = buf[i * st + w];
+  }
+  return MPC_OK;
+}
+
 int obs_all(mpc_sim* s, std::vector<double>& P, std::vector<double>& E,
             std::vector<double>& K) {
   const size_t nbox = s->boxes.size();
@@ -514,12 +535,9 @@ int mpc_create(const mpc_params* p, int32_t nbox, void* workspace, size_t bytes,
   const Plan& P = s->plan;
   char* ws = (char*)workspace;
   for (int b = 0; b < 2; ++b) {
-    for (int k = 0; k < 3; ++k) {
-      s->dev.S[b].a[k] = ws + P.off_S[b][k];
-      s->dev.S[b].b[k] = ws + P.off_S[b][3 + k];
-    }
-    s->dev.S[b].cell = P.split ? (uint32_t*)(ws + P.off_S[b][6]) : nullptr;
-    s->dev.S[b].id = P.ids ? (uint32_t*)(ws + P.off_S[b][7]) : nullptr;
+    s->dev.S[b].rec = ws + P.off_rec[b];
+    s->dev.S[b].id = P.split ? &((RecSplit*)(ws + P.off_rec[b]))->id : (uint32_t*)(ws + P.off_id[b]);
+    s->dev.S[b].id_stride = P.split ? (uint32_t)(sizeof(RecSplit) / 4) : 1u;
   }
   s->dev.key = (uint32_t*)(ws + P.off_key);
   s->dev.perm = (uint32_t*)(ws + P.off_perm);
@@ -841,63 +859,61 @@ int mpc_set_state(mpc_sim* s, int32_t box, const double* x, const double* v, int
     }
   }
   HIPCHK(s, hipStreamSynchronize(s->L.stream));
+  // records (and ids) of the box, packed on the host a chunk at a time
   const StatePtrs& S = s->dev.S[s->cur];
-  int rc = MPC_OK;
-  if (s->form == MPC_FP64) {
-    std::vector<double> buf(n);
-    for (int k = 0; k < 6 && !rc; ++k) {
-      const double* src = k < 3 ? x + k * n : v + (k - 3) * n;
-      for (int64_t i = 0; i < n; ++i) buf[i] = src[i] / a;
-      rc = copy_h2d(s, k < 3 ? S.a[k] : S.b[k - 3], B.pbase, buf);
-      if (!rc) HIPCHK(s, hipStreamSynchronize(s->L.stream));
-    }
-  } else if (s->form == MPC_FP32) {
-    std::vector<float> buf(n);
-    for (int k = 0; k < 6 && !rc; ++k) {
-      const double* src = k < 3 ? x + k * n : v + (k - 3) * n;
-      for (int64_t i = 0; i < n; ++i) {
-        float f = (float)(src[i] / a);
-        if (k < 3 && !(walls && k == 2) && f >= B.Lf[k]) f = nextafterf(B.Lf[k], 0.0f);
-        buf[i] = f;
-      }
-      rc = copy_h2d(s, k < 3 ? S.a[k] : S.b[k - 3], B.pbase, buf);
-      if (!rc) HIPCHK(s, hipStreamSynchronize(s->L.stream));
-    }
-  } else {
-    std::vector<uint32_t> cell(n, 0u);
-    std::vector<float> buf(n);
-    for (int k = 0; k < 3 && !rc; ++k) {
-      const uint32_t shift = k == 0 ? 0 : (k == 1 ? kSplitXBits : kSplitXBits + kSplitYBits);
-      for (int64_t i = 0; i < n; ++i) {
-        const double xi = x[k * n + i] / a;
-        double fl = floor(xi);
-        float o = (float)(xi - fl);
-        if (o >= 1.0f) {
-          o = 0.0f;
-          fl += 1.0;
+  const size_t rb = s->plan.rec;
+  const int64_t chunk = std::min<int64_t>(n, kStateChunk);
+  std::vector<unsigned char> rbuf((size_t)chunk * rb);
+  std::vector<uint32_t> ibuf(s->plan.split ? 0 : (size_t)chunk);
+  for (int64_t i0 = 0; i0 < n; i0 += chunk) {
+    const int64_t m = std::min(chunk, n - i0);
+    for (int64_t i = 0; i < m; ++i) {
+      const int64_t g = i0 + i;
+      const uint32_t id = B.pbase + (uint32_t)g;
+      if (s->form == MPC_FP64) {
+        RecF64& r = ((RecF64*)rbuf.data())[i];
+        for (int k = 0; k < 3; ++k) {
+          r.x[k] = x[k * n + g] / a;
+          r.v[k] = v[k * n + g] / a;
         }
-        int c = (int)fl;
-        if (!(walls && k == 2) && c >= B.L[k]) c -= B.L[k];
-        cell[i] |= (uint32_t)c << shift;
-        buf[i] = o;
+        ibuf[i] = id;
+      } else if (s->form == MPC_FP32) {
+        RecF32& r = ((RecF32*)rbuf.data())[i];
+        for (int k = 0; k < 3; ++k) {
+          float f = (float)(x[k * n + g] / a);
+          if (!(walls && k == 2) && f >= B.Lf[k]) f = nextafterf(B.Lf[k], 0.0f);
+          r.x[k] = f;
+          r.v[k] = (float)(v[k * n + g] / a);
+        }
+        ibuf[i] = id;
+      } else {
+        RecSplit& r = ((RecSplit*)rbuf.data())[i];
+        r.cell = 0u;
+        for (int k = 0; k < 3; ++k) {
+          const uint32_t shift = k == 0 ? 0 : (k == 1 ? kSplitXBits : kSplitXBits + kSplitYBits);
+          const double xi = x[k * n + g] / a;
+          double fl = floor(xi);
+          float o = (float)(xi - fl);
+          if (o >= 1.0f) {
+            o = 0.0f;
+            fl += 1.0;
+          }
+          int c = (int)fl;
+          if (!(walls && k == 2) && c >= B.L[k]) c -= B.L[k];
+          r.cell |= (uint32_t)c << shift;
+          r.o[k] = o;
+          r.v[k] = (float)(v[k * n + g] / a);
+        }
+        r.id = id;
       }
-      rc = copy_h2d(s, S.a[k], B.pbase, buf);
-      if (!rc) HIPCHK(s, hipStreamSynchronize(s->L.stream));
     }
-    for (int k = 0; k < 3 && !rc; ++k) {
-      for (int64_t i = 0; i < n; ++i) buf[i] = (float)(v[k * n + i] / a);
-      rc = copy_h2d(s, S.b[k], B.pbase, buf);
-      if (!rc) HIPCHK(s, hipStreamSynchronize(s->L.stream));
-    }
-    if (!rc) rc = copy_h2d(s, S.cell, B.pbase, cell);
+    HIPCHK(s, hipMemcpyAsync((char*)S.rec + (B.pbase + (uint64_t)i0) * rb, rbuf.data(),
+                             (size_t)m * rb, hipMemcpyHostToDevice, s->L.stream));
+    if (!s->plan.split)
+      HIPCHK(s, hipMemcpyAsync(S.id + B.pbase + i0, ibuf.data(), sizeof(uint32_t) * (size_t)m,
+                               hipMemcpyHostToDevice, s->L.stream));
+    HIPCHK(s, hipStreamSynchronize(s->L.stream));  // the staging buffers are reused
   }
-  if (!rc && S.id) {
-    std::vector<uint32_t> ids(n);
-    for (int64_t i = 0; i < n; ++i) ids[i] = B.pbase + (uint32_t)i;
-    rc = copy_h2d(s, S.id, B.pbase, ids);
-    if (!rc) HIPCHK(s, hipStreamSynchronize(s->L.stream));
-  }
-  if (rc) return rc;
   HIPCHK(s, launch_set_ctrl(s->dev, s->L, s->step, s->cur, s->R, 1));
   HIPCHK(s, hipStreamSynchronize(s->L.stream));
   s->keys_valid = false;
@@ -913,51 +929,49 @@ int mpc_get_state(mpc_sim* s, int32_t box, double* x, double* v, int64_t n) {
   if (rc) return rc;
   const double a = s->params[box].a;
   const StatePtrs& S = s->dev.S[s->cur];
-  // logical index of each stored slot of the box
-  std::vector<uint32_t> lid(n);
-  if (S.id) {
-    if ((rc = copy_d2h(s, S.id, B.pbase, lid))) return rc;
+  // records (and ids) of the box, a chunk at a time, each written to the
+  // caller's order given by its logical index
+  const size_t rb = s->plan.rec;
+  const int64_t chunk = std::min<int64_t>(n, kStateChunk);
+  std::vector<unsigned char> rbuf((size_t)chunk * rb);
+  std::vector<uint32_t> ibuf(s->plan.split ? 0 : (size_t)chunk);
+  std::vector<uint8_t> seen(n, 0);
+  for (int64_t i0 = 0; i0 < n; i0 += chunk) {
+    const int64_t m = std::min(chunk, n - i0);
+    HIPCHK(s, hipMemcpyAsync(rbuf.data(), (const char*)S.rec + (B.pbase + (uint64_t)i0) * rb,
+                             (size_t)m * rb, hipMemcpyDeviceToHost, s->L.stream));
+    if (!s->plan.split)
+      HIPCHK(s, hipMemcpyAsync(ibuf.data(), S.id + B.pbase + i0, sizeof(uint32_t) * (size_t)m,
+                               hipMemcpyDeviceToHost, s->L.stream));
     HIPCHK(s, hipStreamSynchronize(s->L.stream));
-    std::vector<uint8_t> seen(n, 0);
-    for (int64_t i = 0; i < n; ++i) {
-      const uint32_t q = lid[i] - B.pbase;
-      if (lid[i] < B.pbase || q >= (uint64_t)n || seen[q]) {
+    for (int64_t i = 0; i < m; ++i) {
+      const uint32_t id = s->plan.split ? ((const RecSplit*)rbuf.data())[i].id : ibuf[i];
+      const uint32_t q = id - B.pbase;
+      if (id < B.pbase || q >= (uint64_t)n || seen[q]) {
         s->err = "logical particle indices are not a permutation";
         return MPC_ESTATE;
       }
       seen[q] = 1;
-      lid[i] = q;
-    }
-  } else {
-    for (int64_t i = 0; i < n; ++i) lid[i] = (uint32_t)i;
-  }
-  if (s->form == MPC_FP64) {
-    std::vector<double> buf(n);
-    for (int k = 0; k < 6; ++k) {
-      if ((rc = copy_d2h(s, k < 3 ? S.a[k] : S.b[k - 3], B.pbase, buf))) return rc;
-      HIPCHK(s, hipStreamSynchronize(s->L.stream));
-      double* dst = k < 3 ? x + k * n : v + (k - 3) * n;
-      for (int64_t i = 0; i < n; ++i) dst[lid[i]] = buf[i] * a;
-    }
-  } else {
-    std::vector<float> buf(n);
-    std::vector<uint32_t> cell;
-    if (s->form == MPC_SPLIT32) {
-      cell.resize(n);
-      if ((rc = copy_d2h(s, S.cell, B.pbase, cell))) return rc;
-      HIPCHK(s, hipStreamSynchronize(s->L.stream));
-    }
-    for (int k = 0; k < 6; ++k) {
-      if ((rc = copy_d2h(s, k < 3 ? S.a[k] : S.b[k - 3], B.pbase, buf))) return rc;
-      HIPCHK(s, hipStreamSynchronize(s->L.stream));
-      double* dst = k < 3 ? x + k * n : v + (k - 3) * n;
-      if (k < 3 && s->form == MPC_SPLIT32) {
-        const uint32_t shift = k == 0 ? 0 : (k == 1 ? kSplitXBits : kSplitXBits + kSplitYBits);
-        const uint32_t mask = k == 2 ? ((1u << kSplitZBits) - 1) : ((1u << kSplitXBits) - 1);
-        for (int64_t i = 0; i < n; ++i)
-          dst[lid[i]] = ((double)((cell[i] >> shift) & mask) + (double)buf[i]) * a;
+      if (s->form == MPC_FP64) {
+        const RecF64& r = ((const RecF64*)rbuf.data())[i];
+        for (int k = 0; k < 3; ++k) {
+          x[k * n + q] = r.x[k] * a;
+          v[k * n + q] = r.v[k] * a;
+        }
+      } else if (s->form == MPC_FP32) {
+        const RecF32& r = ((const RecF32*)rbuf.data())[i];
+        for (int k = 0; k < 3; ++k) {
+          x[k * n + q] = (double)r.x[k] * a;
+          v[k * n + q] = (double)r.v[k] * a;
+        }
       } else {
-        for (int64_t i = 0; i < n; ++i) dst[lid[i]] = (double)buf[i] * a;
+        const RecSplit& r = ((const RecSplit*)rbuf.data())[i];
+        for (int k = 0; k < 3; ++k) {
+          const uint32_t shift = k == 0 ? 0 : (k == 1 ? kSplitXBits : kSplitXBits + kSplitYBits);
+          const uint32_t mask = k == 2 ? ((1u << kSplitZBits) - 1) : ((1u << kSplitXBits) - 1);
+          x[k * n + q] = ((double)((r.cell >> shift) & mask) + (double)r.o[k]) * a;
+          v[k * n + q] = (double)r.v[k] * a;
+        }
       }
     }
   }
@@ -1066,17 +1080,14 @@ int mpc_get_binning(mpc_sim* s, int32_t box, uint32_t* key, uint32_t* perm, uint
   if (rc) return rc;
   // the last step read the buffer that is not current; its ids give the
   // logical order before that step
-  const uint32_t* ids_in = s->dev.S[s->cur ^ 1u].id;
-  HIPCHK(s, launch_canon_perm(s->dev, s->L, ids_in));
+  const StatePtrs& Sin = s->dev.S[s->cur ^ 1u];
+  HIPCHK(s, launch_canon_perm(s->dev, s->L, Sin));
   const BoxDev& B = s->boxes[box];
-  std::vector<uint32_t> off(B.nc + 1), pm(B.np), lid;
+  std::vector<uint32_t> off(B.nc + 1), pm(B.np), lid(B.np);
   if ((rc = copy_d2h(s, s->dev.offset, B.cbase, off))) return rc;
   if ((rc = copy_d2h(s, s->dev.perm, B.pbase, pm))) return rc;
-  if (ids_in) {
-    lid.resize(B.np);
-    if ((rc = copy_d2h(s, ids_in, B.pbase, lid))) return rc;
-  }
   HIPCHK(s, hipStreamSynchronize(s->L.stream));
+  if ((rc = read_ids(s, Sin, B.pbase, lid))) return rc;
   const uint32_t o0 = off[0];
   for (auto& o : off) o -= o0;
   for (auto& q : pm) {
@@ -1084,7 +1095,7 @@ int mpc_get_binning(mpc_sim* s, int32_t box, uint32_t* key, uint32_t* perm, uint
       s->err = "permutation entry outside the box";
       return MPC_ESTATE;
     }
-    q = ids_in ? lid[q - B.pbase] - B.pbase : q - B.pbase;
+    q = lid[q - B.pbase] - B.pbase;
     if (q >= B.np) {
       s->err = "logical particle index outside the box";
       return MPC_ESTATE;
@@ -1112,10 +1123,8 @@ int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* 
   // host memory if the device has no room) and restored before every trial
   std::vector<std::pair<void*, size_t>> arrs;
   const StatePtrs& S = s->dev.S[cur0];
-  for (int k = 0; k < 3; ++k) arrs.push_back({S.a[k], P.state_elem_a * P.ntot});
-  for (int k = 0; k < 3; ++k) arrs.push_back({S.b[k], P.state_elem_b * P.ntot});
-  if (S.cell) arrs.push_back({S.cell, 4 * P.ntot});
-  if (S.id) arrs.push_back({S.id, 4 * P.ntot});
+  arrs.push_back({S.rec, P.rec * P.ntot});
+  if (!P.split) arrs.push_back({S.id, 4 * P.ntot});
   size_t total = 0;
   for (auto& a : arrs) total += align256(a.second);
   void* backup = nullptr;

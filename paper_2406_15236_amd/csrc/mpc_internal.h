@@ -85,18 +85,41 @@ struct PhantomSums {   // phantom particles of an occupied wall-cut cell
   double pad;
 };
 
-// State buffers of one form, SoA.  F64: a[0..2]=x (double), b[0..2]=v (double);
-// F32: x, v float; Split: cell (u32), a = offsets (float), b = v (float).
-// Every step writes the state into the other buffer, cell by cell of the
-// current step, and inside the particles of one tile pass grouped by their
-// cell of the next step (so that the next step gathers contiguous runs).
-// `id` holds each stored particle's logical index: its index in the caller's
-// order, renumbered to the (cell, index) order on reorder steps.
+// Particle records, one per storage slot (array of structures): the collide
+// gathers a particle with one or two 16-byte loads per 16 bytes of record, so
+// that a run of consecutive slots is one contiguous span of memory instead of
+// one span per component.  Positions and velocities are in cell units.
+struct alignas(16) RecF64 {
+  double x[3];
+  double v[3];
+};
+struct alignas(8) RecF32 {
+  float x[3];
+  float v[3];
+};
+struct alignas(16) RecSplit {
+  uint32_t cell;  // x | y << 11 | z << 22
+  float o[3];     // offsets inside the cell, [0, 1)
+  float v[3];
+  uint32_t id;    // logical index of the particle in this slot
+};
+static_assert(sizeof(RecF64) == 48 && sizeof(RecF32) == 24 && sizeof(RecSplit) == 32,
+              "record sizes");
+constexpr size_t rec_bytes(int form) {
+  return form == kFormF64 ? sizeof(RecF64) : (form == kFormF32 ? sizeof(RecF32) : sizeof(RecSplit));
+}
+
+// One state buffer.  Every step writes the state into the other buffer, cell
+// by cell of the current step, and inside the particles of one tile pass
+// grouped by their cell of the next step (so that the next step gathers
+// contiguous runs).  The logical index of slot i (its index in the caller's
+// order, renumbered to the (cell, index) order on reorder steps) is
+// id[i * id_stride]: an array of its own for FP64 and FP32 (stride 1), the id
+// word of the record for the split form (stride 8).
 struct StatePtrs {
-  void* a[3];
-  void* b[3];
-  uint32_t* cell;
+  void* rec;
   uint32_t* id;
+  uint32_t id_stride;
 };
 
 struct Dev {           // device pointers carved from the workspace
@@ -156,7 +179,7 @@ hipError_t launch_load_f64(const Dev& d, const Launch& l, const double* x, const
                            uint32_t n, double a, uint32_t cur);
 hipError_t launch_store_f64(const Dev& d, const Launch& l, double* x, double* v, uint32_t n,
                             double a, uint32_t cur);
-hipError_t launch_canon_perm(const Dev& d, const Launch& l, const uint32_t* ids);
+hipError_t launch_canon_perm(const Dev& d, const Launch& l, const StatePtrs& ids);
 hipError_t collide_occupancy(const Launch& l, int* blocks_per_cu);  // flags of l only
 
 }  // namespace mpc

@@ -511,19 +511,28 @@ struct Form<kFormF64> {
     p.x[1] = x1[q];
     p.x[2] = x2[q];
   }
+  // record: three 16-byte words (x0 x1 | x2 v0 | v1 v2)
   __device__ static void load(const StatePtrs& S, uint32_t i, P& p, Vv& v) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      p.x[k] = ((const double*)S.a[k])[i];
-      v.v[k] = ((const double*)S.b[k])[i];
-    }
+    const double2* r = (const double2*)S.rec + 3 * (size_t)i;
+    const double2 a = r[0], b = r[1], c = r[2];
+    p.x[0] = a.x;
+    p.x[1] = a.y;
+    p.x[2] = b.x;
+    v.v[0] = b.y;
+    v.v[1] = c.x;
+    v.v[2] = c.y;
   }
-  __device__ static void store(const StatePtrs& S, uint32_t j, const P& p, const Vv& v) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      ((double*)S.a[k])[j] = p.x[k];
-      ((double*)S.b[k])[j] = v.v[k];
-    }
+  __device__ static void load_all(const StatePtrs& S, uint32_t i, P& p, Vv& v, uint32_t& id) {
+    load(S, i, p, v);
+    id = S.id[i];
+  }
+  __device__ static void store_all(const StatePtrs& S, uint32_t j, const P& p, const Vv& v,
+                                   uint32_t id) {
+    double2* r = (double2*)S.rec + 3 * (size_t)j;
+    r[0] = make_double2(p.x[0], p.x[1]);
+    r[1] = make_double2(p.x[2], v.v[0]);
+    r[2] = make_double2(v.v[1], v.v[2]);
+    S.id[j] = id;
   }
   template <bool W>
   __device__ static void stream(P& p, Vv& v, BoxRef B, double dle, bool le) {
@@ -573,19 +582,28 @@ struct Form<kFormF32> {
     p.x[1] = x1[q];
     p.x[2] = x2[q];
   }
+  // record: three 8-byte words (x0 x1 | x2 v0 | v1 v2)
   __device__ static void load(const StatePtrs& S, uint32_t i, P& p, Vv& v) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      p.x[k] = ((const float*)S.a[k])[i];
-      v.v[k] = ((const float*)S.b[k])[i];
-    }
+    const float2* r = (const float2*)S.rec + 3 * (size_t)i;
+    const float2 a = r[0], b = r[1], c = r[2];
+    p.x[0] = a.x;
+    p.x[1] = a.y;
+    p.x[2] = b.x;
+    v.v[0] = b.y;
+    v.v[1] = c.x;
+    v.v[2] = c.y;
   }
-  __device__ static void store(const StatePtrs& S, uint32_t j, const P& p, const Vv& v) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      ((float*)S.a[k])[j] = p.x[k];
-      ((float*)S.b[k])[j] = v.v[k];
-    }
+  __device__ static void load_all(const StatePtrs& S, uint32_t i, P& p, Vv& v, uint32_t& id) {
+    load(S, i, p, v);
+    id = S.id[i];
+  }
+  __device__ static void store_all(const StatePtrs& S, uint32_t j, const P& p, const Vv& v,
+                                   uint32_t id) {
+    float2* r = (float2*)S.rec + 3 * (size_t)j;
+    r[0] = make_float2(p.x[0], p.x[1]);
+    r[1] = make_float2(p.x[2], v.v[0]);
+    r[2] = make_float2(v.v[1], v.v[2]);
+    S.id[j] = id;
   }
   template <bool W>
   __device__ static void stream(P& p, Vv& v, BoxRef B, double dle, bool le) {
@@ -636,21 +654,30 @@ struct Form<kFormSplit> {
     p.o[2] = x2[q];
     p.cell = c[q];
   }
-  __device__ static void load(const StatePtrs& S, uint32_t i, P& p, Vv& v) {
-    p.cell = S.cell[i];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      p.o[k] = ((const float*)S.a[k])[i];
-      v.v[k] = ((const float*)S.b[k])[i];
-    }
+  // record: two 16-byte words (cell o0 o1 o2 | v0 v1 v2 id)
+  __device__ static void load_all(const StatePtrs& S, uint32_t i, P& p, Vv& v, uint32_t& id) {
+    const uint4* r = (const uint4*)S.rec + 2 * (size_t)i;
+    const uint4 a = r[0], b = r[1];
+    p.cell = a.x;
+    p.o[0] = __uint_as_float(a.y);
+    p.o[1] = __uint_as_float(a.z);
+    p.o[2] = __uint_as_float(a.w);
+    v.v[0] = __uint_as_float(b.x);
+    v.v[1] = __uint_as_float(b.y);
+    v.v[2] = __uint_as_float(b.z);
+    id = b.w;
   }
-  __device__ static void store(const StatePtrs& S, uint32_t j, const P& p, const Vv& v) {
-    S.cell[j] = p.cell;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      ((float*)S.a[k])[j] = p.o[k];
-      ((float*)S.b[k])[j] = v.v[k];
-    }
+  __device__ static void load(const StatePtrs& S, uint32_t i, P& p, Vv& v) {
+    uint32_t id;
+    load_all(S, i, p, v, id);
+  }
+  __device__ static void store_all(const StatePtrs& S, uint32_t j, const P& p, const Vv& v,
+                                   uint32_t id) {
+    uint4* r = (uint4*)S.rec + 2 * (size_t)j;
+    r[0] = make_uint4(p.cell, __float_as_uint(p.o[0]), __float_as_uint(p.o[1]),
+                      __float_as_uint(p.o[2]));
+    r[1] = make_uint4(__float_as_uint(v.v[0]), __float_as_uint(v.v[1]), __float_as_uint(v.v[2]),
+                      id);
   }
   template <bool W>
   __device__ static void stream(P& p, Vv& v, BoxRef B, double dle, bool le) {
@@ -1621,7 +1648,6 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
   const bool renumber = R > 0 && (t + 1) % (uint64_t)R == 0;
   const StatePtrs in = d.S[cur];
   const StatePtrs out = d.S[cur ^ 1u];
-  const bool track = in.id != nullptr;
   uint32_t err = 0;
   const uint32_t lane = threadIdx.x;
 
@@ -1732,11 +1758,11 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
           if (live) {
             typename Fm::P p;
             typename Fm::Vv v;
-            Fm::load(in, i, p, v);
+            uint32_t id;
+            Fm::load_all(in, i, p, v, id);
             Fm::template stream<W>(p, v, B, s_sh[6], E && B.le);
             const uint32_t j = base + q;
-            Fm::store(out, j, p, v);
-            if (track) out.id[j] = renumber ? j : in.id[i];
+            Fm::store_all(out, j, p, v, renumber ? j : id);
             Fm::template stream<W>(p, v, B, s_sh[7], E && B.le);
             kn = B.cbase + Fm::template key<W>(p, snx, B, err, s_sh[7], E && B.le);
             d.key[j] = kn;
@@ -1780,8 +1806,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
           idk[k] = 0;
           if (q < np) {
             ii[k] = s_idx[q] < d.ntot ? s_idx[q] : 0u;
-            Fm::load(in, ii[k], p[k], v[k]);
-            if (track) idk[k] = in.id[ii[k]];
+            Fm::load_all(in, ii[k], p[k], v[k], idk[k]);
           }
         }
         // prefetch the next tile's first-pass perm entries and cell draws
@@ -1799,24 +1824,21 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
           if (lane < Tn.nc) draw_next = d.draws[Tn.c0 + lane];
         }
         __builtin_amdgcn_s_setprio(0);
-        if (track) {
 #pragma unroll
-          for (int k = 0; k < NS; ++k) {
-            const uint32_t q = lane + k * NT;
-            if (q < np) s_rk[q] = idk[k];
-          }
-          wave_sync();
+        for (int k = 0; k < NS; ++k) {
+          const uint32_t q = lane + k * NT;
+          if (q < np) s_rk[q] = idk[k];
         }
+        wave_sync();
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
           const uint32_t q = lane + k * NT;
           __builtin_amdgcn_sched_barrier(0);
           if (q < np) {
-            const uint32_t i = ii[k];
             const uint32_t c = cs + s_lc[q];
             const uint32_t b = s_off[c] - base, e = s_off[c + 1] - base;
-            const uint32_t id = track ? s_rk[q] : i;
-            const uint32_t qc = b + rank_in_segment(track ? s_rk : s_idx, b, e, id);
+            const uint32_t id = s_rk[q];
+            const uint32_t qc = b + rank_in_segment(s_rk, b, e, id);
             Fm::template stream<W>(p[k], v[k], B, s_sh[6], E && B.le);
             if constexpr (E) {
               const int side = B.le ? Fm::le_side(p[k], s_sh[2], B) : 0;
@@ -2016,8 +2038,7 @@ void k_collide(Dev d, uint32_t ntiles, int xcd_remap) {
             v.v[0] = s_v[0][q];
             v.v[1] = s_v[1][q];
             v.v[2] = s_v[2][q];
-            Fm::store(out, j, p, v);
-            if (track) out.id[j] = renumber ? base + q : s_idc[q];
+            Fm::store_all(out, j, p, v, renumber ? base + q : s_idc[q]);
             d.key[j] = kn;
             // leaving the window: counted one by one
             if ((pk >> 16) == (uint32_t)(9 * WX))
@@ -2133,15 +2154,16 @@ hipError_t collide_occupancy(const Launch& l, int* blocks_per_cu) {
 
 // ---------------------------------------------------------------------------
 // Canonical permutation for export: sort each cell segment by logical index
-// (ids[slot], or the slot itself when ids is null).
+// (ids[slot * stride], or the slot itself when ids is null).
 // ---------------------------------------------------------------------------
 __global__ void k_canon_perm(uint32_t* __restrict__ perm, const uint32_t* __restrict__ offset,
-                             uint64_t ncell, uint32_t n, const uint32_t* __restrict__ ids) {
+                             uint64_t ncell, uint32_t n, const uint32_t* __restrict__ ids,
+                             uint32_t stride) {
   const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
   const uint32_t b = offset[c], e = offset[c + 1];
   if (e > n || b > e) return;
-  auto rk = [&](uint32_t slot) { return ids && slot < n ? ids[slot] : slot; };
+  auto rk = [&](uint32_t slot) { return ids && slot < n ? ids[(size_t)slot * stride] : slot; };
   for (uint32_t i = b + 1; i < e; ++i) {
     const uint32_t x = perm[i];
     const uint32_t kx = rk(x);
@@ -2160,12 +2182,12 @@ __global__ void k_canon_perm(uint32_t* __restrict__ perm, const uint32_t* __rest
 // cell + offset is exact in FP64).  A logical index with no stored slot
 // yields NaN.
 // ---------------------------------------------------------------------------
-__global__ void k_invert_ids(const uint32_t* __restrict__ id, uint32_t pbase, uint32_t np,
-                             uint32_t* __restrict__ inv) {
+__global__ void k_invert_ids(const uint32_t* __restrict__ id, uint32_t id_stride, uint32_t pbase,
+                             uint32_t np, uint32_t* __restrict__ inv) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < np; q += stride) {
     const uint32_t j = pbase + (uint32_t)q;
-    const uint32_t l = id[j] - pbase;
+    const uint32_t l = id[(size_t)j * id_stride] - pbase;
     if (l < np) inv[l] = j;
   }
 }
@@ -2186,18 +2208,27 @@ __global__ __launch_bounds__(kThreads) void k_gather_particles(StatePtrs S,
 #pragma unroll
     for (int c = 0; c < 6; ++c) r[c] = __builtin_nan("");
   } else if constexpr (F == kFormF64) {
+    const RecF64 q = ((const RecF64*)S.rec)[j];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      r[c] = ((const double*)S.a[c])[j];
-      r[3 + c] = ((const double*)S.b[c])[j];
+      r[c] = q.x[c];
+      r[3 + c] = q.v[c];
+    }
+  } else if constexpr (F == kFormF32) {
+    const RecF32 q = ((const RecF32*)S.rec)[j];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      r[c] = (double)q.x[c];
+      r[3 + c] = (double)q.v[c];
     }
   } else {
-    int ci[3] = {0, 0, 0};
-    if constexpr (F == kFormSplit) split_decode(S.cell[j], ci);
+    const RecSplit q = ((const RecSplit*)S.rec)[j];
+    int ci[3];
+    split_decode(q.cell, ci);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      r[c] = (double)ci[c] + (double)((const float*)S.a[c])[j];
-      r[3 + c] = (double)((const float*)S.b[c])[j];
+      r[c] = (double)ci[c] + (double)q.o[c];
+      r[3 + c] = (double)q.v[c];
     }
   }
 #pragma unroll
@@ -2219,16 +2250,18 @@ __global__ __launch_bounds__(kThreads) void k_load_f64(Dev d, const double* __re
   BoxRef B = as_const(d.boxes)[0];
   const StatePtrs S = d.S[cur];
   bool ok = true;
+  RecF64 r;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const double xi = x[(uint64_t)k * n + i] / a;
     const double vi = v[(uint64_t)k * n + i] / a;
     const bool in = (B.walls && k == 2) ? (xi >= 0.0 && xi <= B.Ld[k]) : (xi >= 0.0 && xi < B.Ld[k]);
     ok = ok && in && isfinite(vi);
-    ((double*)S.a[k])[i] = in ? xi : 0.0;
-    ((double*)S.b[k])[i] = isfinite(vi) ? vi : 0.0;
+    r.x[k] = in ? xi : 0.0;
+    r.v[k] = isfinite(vi) ? vi : 0.0;
   }
-  if (S.id) S.id[i] = i;
+  ((RecF64*)S.rec)[i] = r;
+  S.id[i] = i;
   if (!ok) atomicOr(&d.ctrl->err, kErrKey);
 }
 
@@ -2238,12 +2271,13 @@ __global__ __launch_bounds__(kThreads) void k_store_f64(Dev d, double* __restric
   const uint32_t j = blockIdx.x * kThreads + threadIdx.x;
   if (j >= n) return;
   const StatePtrs S = d.S[cur];
-  const uint32_t l = S.id ? S.id[j] : j;
+  const uint32_t l = S.id[j];
   if (l >= n) return;
+  const RecF64 r = ((const RecF64*)S.rec)[j];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    x[(uint64_t)k * n + l] = ((const double*)S.a[k])[j] * a;
-    v[(uint64_t)k * n + l] = ((const double*)S.b[k])[j] * a;
+    x[(uint64_t)k * n + l] = r.x[k] * a;
+    v[(uint64_t)k * n + l] = r.v[k] * a;
   }
 }
 
@@ -2261,7 +2295,6 @@ __global__ __launch_bounds__(kThreads) void k_init_state(Dev d, uint32_t k0, uin
     const uint32_t i = pb.p0 + s * kThreads + threadIdx.x;
     if (i >= pend) continue;
     const uint32_t li = i - B.pbase;
-    if (S.id) S.id[i] = i;
     const Words4 a = philox10(0, li, pb.box, kTagInitPos, k0, k1);
     const Words4 b = philox10(1, li, pb.box, kTagInitPos, k0, k1);
     double x[3] = {u53_of(a.w[0], a.w[1]) * B.Ld[0], u53_of(a.w[2], a.w[3]) * B.Ld[1],
@@ -2276,20 +2309,27 @@ __global__ __launch_bounds__(kThreads) void k_init_state(Dev d, uint32_t k0, uin
     const double t1 = kTwoPi * ((double)c.w[3] * 0x1p-32);
     const double v[3] = {B.sd * r0 * cos(t0), B.sd * r0 * sin(t0), B.sd * r1 * cos(t1)};
     if constexpr (F == kFormF64) {
+      RecF64 r;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        ((double*)S.a[k])[i] = x[k];
-        ((double*)S.b[k])[i] = v[k];
+        r.x[k] = x[k];
+        r.v[k] = v[k];
       }
+      ((RecF64*)S.rec)[i] = r;
+      S.id[i] = i;
     } else if constexpr (F == kFormF32) {
+      RecF32 r;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         float xf = (float)x[k];
         if (xf >= B.Lf[k]) xf = nextafterf(B.Lf[k], 0.0f);
-        ((float*)S.a[k])[i] = xf;
-        ((float*)S.b[k])[i] = (float)v[k];
+        r.x[k] = xf;
+        r.v[k] = (float)v[k];
       }
+      ((RecF32*)S.rec)[i] = r;
+      S.id[i] = i;
     } else {
+      RecSplit r;
       int c3[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -2299,10 +2339,12 @@ __global__ __launch_bounds__(kThreads) void k_init_state(Dev d, uint32_t k0, uin
           c3[k] = B.L[k] - 1;
           o = nextafterf(1.0f, 0.0f);
         }
-        ((float*)S.a[k])[i] = o;
-        ((float*)S.b[k])[i] = (float)v[k];
+        r.o[k] = o;
+        r.v[k] = (float)v[k];
       }
-      S.cell[i] = split_encode(c3);
+      r.cell = split_encode(c3);
+      r.id = i;
+      ((RecSplit*)S.rec)[i] = r;
     }
   }
 }
@@ -2314,11 +2356,17 @@ __global__ __launch_bounds__(kThreads) void k_init_state(Dev d, uint32_t k0, uin
 template <int F>
 __device__ __forceinline__ void load_vel_d(const StatePtrs& S, uint32_t i, double (&v)[3]) {
   if constexpr (F == kFormF64) {
+    const RecF64& r = ((const RecF64*)S.rec)[i];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) v[k] = ((const double*)S.b[k])[i];
+    for (int k = 0; k < 3; ++k) v[k] = r.v[k];
+  } else if constexpr (F == kFormF32) {
+    const RecF32& r = ((const RecF32*)S.rec)[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = (double)r.v[k];
   } else {
+    const RecSplit& r = ((const RecSplit*)S.rec)[i];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) v[k] = (double)((const float*)S.b[k])[i];
+    for (int k = 0; k < 3; ++k) v[k] = (double)r.v[k];
   }
 }
 
@@ -2393,11 +2441,14 @@ __global__ __launch_bounds__(kThreads) void k_remove_mean(Dev d, const double* v
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       if constexpr (F == kFormF64) {
-        double* p = (double*)S.b[k];
-        p[i] = p[i] - V[k];
+        double* p = ((RecF64*)S.rec)[i].v;
+        p[k] = p[k] - V[k];
+      } else if constexpr (F == kFormF32) {
+        float* p = ((RecF32*)S.rec)[i].v;
+        p[k] = (float)((double)p[k] - V[k]);
       } else {
-        float* p = (float*)S.b[k];
-        p[i] = (float)((double)p[i] - V[k]);
+        float* p = ((RecSplit*)S.rec)[i].v;
+        p[k] = (float)((double)p[k] - V[k]);
       }
     }
   }
@@ -2484,11 +2535,11 @@ hipError_t launch_collide(const Dev& d, const Launch& l) {
   return collide_dispatch<CollideLaunchOp>(d, l, nullptr);
 }
 
-hipError_t launch_canon_perm(const Dev& d, const Launch& l, const uint32_t* ids) {
+hipError_t launch_canon_perm(const Dev& d, const Launch& l, const StatePtrs& ids) {
   const uint64_t blocks = (l.ctot + kThreads - 1) / kThreads;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_canon_perm, dim3((uint32_t)blocks), dim3(kThreads), 0, l.stream, d.perm,
-                     d.offset, l.ctot, (uint32_t)l.ntot, ids);
+                     d.offset, l.ctot, (uint32_t)l.ntot, (const uint32_t*)ids.id, ids.id_stride);
   return hipGetLastError();
 }
 
@@ -2500,8 +2551,8 @@ hipError_t launch_gather_particles(const Dev& d, const Launch& l, const StatePtr
   if (inv) {
     uint64_t blocks = ((uint64_t)np + kThreads - 1) / kThreads;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_invert_ids, dim3((uint32_t)blocks), dim3(kThreads), 0, l.stream, S.id,
-                       pbase, np, inv);
+    hipLaunchKernelGGL(k_invert_ids, dim3((uint32_t)blocks), dim3(kThreads), 0, l.stream,
+                       (const uint32_t*)S.id, S.id_stride, pbase, np, inv);
   }
   MPC_FORM_DISPATCH(l.form, k_gather_particles, dim3((m + kThreads - 1) / kThreads),
                     dim3(kThreads), 0, l.stream, S, inv, pbase, np, lidx, m, out);
