@@ -252,7 +252,8 @@ int mpc_get_binning(mpc_sim* s, int32_t box, uint32_t* key, uint32_t* perm, uint
 
 /* Autotuner: choose the collide tiling (cells per tile, persistent grid size,
  * rows per block of the tile order) by timing trial_steps steps (1..1000) of
- * each candidate from the current state, in a coordinate search (tile size,
+ * each candidate from the current state (a candidate counts with its fastest
+ * step), in a coordinate search (tile size,
  * then grid, then row block, then the x-segment-major order with each row
  * block).  Before every trial and at the end the state
  * and step counter are restored from a copy, so the random streams and all

@@ -1172,8 +1172,9 @@ int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* 
     return hip_fail(s, e0, "autotune backup");
   }
   // one trial: set the tiling, one untimed step (binning prologue), then
-  // trial_steps timed steps; returns milliseconds per step
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  // trial_steps timed steps; returns the fastest step in milliseconds (the
+  // minimum is robust to a step slowed by other work on the device)
+  std::vector<hipEvent_t> ev((size_t)trial_steps + 1, nullptr);
   auto trial = [&](int T, int g, int yb, int ord, double* ms) -> int {
     int r = mpc_set_tiling(s, T, g, yb, ord);
     if (r) return r;
@@ -1182,17 +1183,24 @@ int mpc_autotune(mpc_sim* s, int32_t trial_steps, int32_t* tile_cells, int32_t* 
     HIPCHK(s, enqueue_step(s, st));
     advance_mirror(s, 1);
     HIPCHK(s, hipEventRecord(ev[0], st));
-    for (int32_t k = 0; k < trial_steps; ++k) HIPCHK(s, enqueue_step(s, st));
-    HIPCHK(s, hipEventRecord(ev[1], st));
-    HIPCHK(s, hipEventSynchronize(ev[1]));
+    for (int32_t k = 0; k < trial_steps; ++k) {
+      HIPCHK(s, enqueue_step(s, st));
+      HIPCHK(s, hipEventRecord(ev[(size_t)k + 1], st));
+    }
+    HIPCHK(s, hipEventSynchronize(ev[(size_t)trial_steps]));
     advance_mirror(s, trial_steps);
-    float f = 0.f;
-    HIPCHK(s, hipEventElapsedTime(&f, ev[0], ev[1]));
-    *ms = (double)f / trial_steps;
+    double m = 1e300;
+    for (int32_t k = 0; k < trial_steps; ++k) {
+      float f = 0.f;
+      HIPCHK(s, hipEventElapsedTime(&f, ev[(size_t)k], ev[(size_t)k + 1]));
+      m = std::min(m, (double)f);
+    }
+    *ms = m;
     return check_sticky(s);
   };
   rc = MPC_OK;
-  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) rc = MPC_EHIP;
+  for (hipEvent_t& x : ev)
+    if (!rc && hipEventCreate(&x) != hipSuccess) rc = MPC_EHIP;
   int bestT = T0, bestG = g0, bestY = y0, bestO = o0;
   double best = 1e300;
   // coordinate search: tile size, then the persistent grid, then the row block
