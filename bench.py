@@ -45,7 +45,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0                       # MI355X HBM3E peak, GB/s
 STATE_BYTES = {"fp64": 48, "fp32": 24, "split": 28}   # stored bytes per particle
 METRIC = "MPC particle-steps/s on 1 GPU + % HBM roofline, FP64 vs split-FP32 vs batched"
-DEFAULT_FORMS = "split,c2_fp64,c2_fp32,c2_split,batched,batched_split,amc,amc_split"
+DEFAULT_FORMS = "split,c2_fp64,c2_fp32,c2_split,batched,batched_split,amc,amc_split,c5"
 
 
 def log(msg: str):
