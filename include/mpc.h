@@ -55,9 +55,9 @@ typedef enum {
   MPC_FP32 = 1,    /* x, v in FP32 (24-byte record); streamed in FP32, cell sums and
                       rotation in FP64                                                 */
   MPC_SPLIT32 = 2  /* packed int32 cell index + FP32 offset in [0,1) per axis, FP32
-                      velocities and the particle's index in one 32-byte record, FP32
-                      velocities; streaming and rotation in FP32 with compensated FP32
-                      cell sums; thermostat energy and kappa in FP64                   */
+                      velocities and the particle's index in one 32-byte record;
+                      streaming and the per-particle rotation in FP32; cell sums,
+                      thermostat energy and kappa in FP64                              */
 } mpc_form;
 
 /* Feature flags (identical for all boxes of one handle). */
