@@ -270,7 +270,7 @@ def run_reorder_sweep(mpc, torch, synth, steps: int = 200):
         out[str(R) if R else "never"] = wall * 1e3 / steps
     log("[reorder sweep] " + ", ".join(f"R={k}: {v:.3f}" for k, v in out.items()) + " ms/step")
     return {"workload": "128^3 cells, 10/cell, FP64, SRD+a + MBS, "
-                        f"{steps} steps per interval", "ms_per_step": out}
+                        f"{steps} steps per interval", "ms_per_step_by_interval": out}
 
 
 def cpu_baseline(steps: int = 3):
@@ -471,7 +471,7 @@ def main():
                 forms["c5"] = run_c5(mpc, torch, synth, args.c5_steps)
             else:
                 raise ValueError(f"unknown form {form}")
-            if form in forms and "ms_per_step" in forms[form]:
+            if form in forms and isinstance(forms[form].get("ms_per_step"), float):
                 log(f"[{form}] {forms[form]['ms_per_step']:.3f} ms/step"
                     + (f", collide {forms[form]['collide_ms']:.3f} ms"
                        if "collide_ms" in forms[form] else ""))
