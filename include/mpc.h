@@ -223,7 +223,11 @@ int mpc_set_step(mpc_sim* s, uint64_t step);
  * Conversions: FP64 exact; FP32 rounds to nearest; SPLIT32 stores
  * cell = floor(x/a), offset = (float)(x/a - cell) (an offset that rounds to 1
  * moves to the next cell).  get returns the exact FP64 value of what is
- * stored.  Both synchronise. */
+ * stored.  Both synchronise and move the box through host staging buffers a
+ * few million particles at a time.  get returns MPC_ESTATE if the stored
+ * logical indices are not a permutation of [0, n) (x and v then hold only
+ * part of the state); set leaves the state unchanged on MPC_EINVAL (the
+ * positions are checked before anything is copied). */
 int mpc_set_state(mpc_sim* s, int32_t box, const double* x, const double* v, int64_t n);
 int mpc_get_state(mpc_sim* s, int32_t box, double* x, double* v, int64_t n);
 

@@ -62,6 +62,7 @@ def load(path: str | None = None) -> dict:
 def save(data: dict, path: str | None = None) -> bool:
     """Write the cache atomically; False if the location is not writable."""
     p = cache_path(path)
+    tmp = None
     try:
         fd, tmp = tempfile.mkstemp(prefix=".tuning", dir=os.path.dirname(p) or ".")
         with os.fdopen(fd, "w") as f:
@@ -69,6 +70,11 @@ def save(data: dict, path: str | None = None) -> bool:
         os.replace(tmp, p)
         return True
     except OSError:
+        if tmp is not None and os.path.exists(tmp):
+            try:
+                os.unlink(tmp)
+            except OSError:
+                pass
         return False
 
 
