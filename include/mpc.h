@@ -56,8 +56,8 @@ typedef enum {
                       rotation in FP64                                                 */
   MPC_SPLIT32 = 2  /* packed int32 cell index + FP32 offset in [0,1) per axis, FP32
                       velocities and the particle's index in one 32-byte record;
-                      streaming and the per-particle rotation in FP32; cell sums,
-                      thermostat energy and kappa in FP64                              */
+                      streaming and rotation in FP32 with compensated FP32 momentum
+                      sums per cell; thermostat energy and kappa in FP64               */
 } mpc_form;
 
 /* Feature flags (identical for all boxes of one handle). */

@@ -1297,9 +1297,44 @@ __device__ void cell_work(BoxRef B, uint32_t lkey, double sz, const CellDraw& cd
     V[0] = P[0] / Mtot;
     V[1] = P[1] / Mtot;
     V[2] = P[2] / Mtot;
+  } else if constexpr (F == kFormSplit) {
+    // compensated FP32 momentum sums (Neumaier)
+    const float mf = (float)m;
+    float s[3] = {0.f, 0.f, 0.f}, c[3] = {0.f, 0.f, 0.f};
+    auto add = [&](int k, float x) {
+      const float tt = s[k] + x;
+      if (fabsf(s[k]) >= fabsf(x)) {
+        c[k] += (s[k] - tt) + x;
+      } else {
+        c[k] += (x - tt) + s[k];
+      }
+      s[k] = tt;
+    };
+#pragma unroll 4
+    for (uint32_t q = qb; q < qe; ++q) {
+      add(0, mf * sv0[q]);
+      add(1, mf * sv1[q]);
+      add(2, mf * sv2[q]);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float os = pair_xor(s[k]), oc = pair_xor(c[k]);
+      // first half's (s, c), then the second half's s added, then its c
+      const float s0 = half ? os : s[k], c0 = half ? oc : c[k];
+      const float s1 = half ? s[k] : os, c1 = half ? c[k] : oc;
+      s[k] = s0;
+      c[k] = c0;
+      add(k, s1);
+      c[k] += c1;
+    }
+    if (W && nph) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) add(k, (float)(m * pv[k]));
+    }
+    const float Mf = (float)(ntot ? ntot : 1u) * mf;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) V[k] = (double)((s[k] + c[k]) / Mf);
   } else {
-    // FP64 sums of the stored velocities (every form: cell quantities are
-    // formed in FP64, Sec. III.G)
     double P[3] = {0.0, 0.0, 0.0};
 #pragma unroll 4
     for (uint32_t q = qb; q < qe; ++q) {
