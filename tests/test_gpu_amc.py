@@ -83,6 +83,8 @@ AMC_CASES = [
     ((10, 10, 10), 2.0, (0, 0, 0), 0, 5, False),         # many cells of one, two, three
     ((10, 10, 10), 2.0, (0, 0, 0), 1, 6, True),
     ((6, 5, 7), 60.0, (0, 0, 0), 1, 1, True),            # tiles in several passes
+    ((1, 1, 1), 10.0, (0, 0, 0), 1, 2, True),            # a single cell
+    ((2, 3, 1), 10.0, (0, 0, 0), 0, 3, False),           # one and two cells per axis
 ]
 
 

@@ -57,6 +57,8 @@ LE_CASES = [
     ((13, 9, 11), 0.8, False, False, (0, 0, 0), 1, 3),
     ((12, 10, 8), 0.3, True, True, (1e-3, 0, 0), 3, 2),
     ((7, 33, 5), 1.7, True, False, (0, 0, 0), 0, 123456),
+    ((4, 3, 2), 0.7, True, False, (0, 0, 0), 1, 4),      # two layers across the shear
+    ((3, 2, 1), 0.4, False, False, (0, 0, 0), 0, 2),     # one layer: its own image
 ]
 
 

@@ -62,6 +62,13 @@ FP64_CASES = [
     ((12, 10, 8), True, True, (2e-3, 0, 0), 0, 2),      # walls + phantoms + gravity
     ((12, 10, 8), True, True, (2e-3, 0, 0), 1, 11),
     ((7, 33, 5), False, False, (0, 0, 0), 0, 123456),   # odd shape, large step index
+    # degenerate boxes: one cell along an axis (every image of a cell is the
+    # cell itself), two cells (the rows on both sides of a tile coincide)
+    ((1, 1, 1), True, False, (0, 0, 0), 1, 4),          # a single cell
+    ((2, 1, 3), False, False, (0, 0, 0), 0, 9),
+    ((1, 6, 2), True, False, (0, 0, 0), 3, 2),
+    ((3, 2, 2), True, True, (1e-3, 0, 0), 0, 5),        # walls, H = 2
+    ((2, 2, 1), True, True, (0, 0, 0), 1, 1),           # walls, H = 1
 ]
 
 
@@ -112,11 +119,14 @@ def test_fp64_c1_100_steps_graph(mpc):
     assert o1["T"] == pytest.approx(oo["T"], rel=1e-12)
 
 
-@pytest.mark.parametrize("form,walls,R", [("fp32", False, 0), ("split", False, 0),
-                                          ("split", False, 1), ("fp32", True, 0),
-                                          ("split", True, 0)])
-def test_reduced_precision_one_step(mpc, form, walls, R):
-    L = (16, 12, 10)
+@pytest.mark.parametrize("form,walls,R,L", [("fp32", False, 0, (16, 12, 10)),
+                                            ("split", False, 0, (16, 12, 10)),
+                                            ("split", False, 1, (16, 12, 10)),
+                                            ("fp32", True, 0, (16, 12, 10)),
+                                            ("split", True, 0, (16, 12, 10)),
+                                            ("split", False, 1, (1, 2, 3)),   # degenerate
+                                            ("fp32", True, 0, (2, 1, 2))])
+def test_reduced_precision_one_step(mpc, form, walls, R, L):
     box = box_of(L, mbs=True, walls=walls, g=(1e-3, 0, 0) if walls else (0, 0, 0), seed=9)
     x, v = synth.box_state(L, seed=21)
     t0 = 4

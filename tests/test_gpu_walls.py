@@ -58,6 +58,8 @@ WALL_CASES = [
     ((12, 10, 8), False, 0.3, True, (0, 0, 0), 0, 3),
     ((13, 9, 7), False, 0.5, True, (1e-3, 0, 0), 1, 8),
     ((16, 16, 6), False, 0.2, False, (0, 0, 0), 3, 2),
+    ((3, 2, 2), True, 0.0, True, (1e-3, 0, 0), 0, 2),     # slip walls, H = 2
+    ((2, 2, 1), False, 0.3, True, (0, 0, 0), 1, 1),       # moving walls, H = 1
 ]
 
 
