@@ -229,6 +229,59 @@ def test_batched_parity(mpc):
         assert e.max() <= 1e-12, (i, e.max())
 
 
+@pytest.mark.parametrize("form", ["fp64", "split"])
+def test_batched_degenerate_boxes(mpc, form):
+    """A batch that mixes a single-cell box, boxes one or two cells thick and
+    an ordinary box: each box equals its own oracle step (the reduced form:
+    binning bit-identical given the GPU's post-stream state, e <= 2e-6)."""
+    shapes = [(1, 1, 1), (2, 3, 1), (1, 4, 2), (9, 7, 6), (3, 1, 2)]
+    boxes = [box_of(L, mbs=True, seed=40 + i, kT=0.5 + 0.3 * i)  # flags equal per handle
+             for i, L in enumerate(shapes)]
+    states = [synth.box_state(b["L"], density=b["density"], kT=b["kT"], seed=200 + i)
+              for i, b in enumerate(boxes)]
+    t0 = 6
+    with mpc.Sim(boxes, form=form, reorder_every=1) as sim:
+        stored = []
+        for i, (x, v) in enumerate(states):
+            sim.set_state(x, v, box=i)
+            stored.append(sim.get_state(box=i))
+        sim.set_step(t0)
+        sim.step(1)
+        outs = [sim.get_state(box=i) for i in range(len(boxes))]
+        bins = [sim.get_binning(box=i) for i in range(len(boxes))]
+    for i, b in enumerate(boxes):
+        x, v = stored[i] if form == "split" else states[i]
+        p = oparams(b)
+        kg, pg, og = bins[i]
+        if form == "fp64":
+            xo, vo, ko, po, oo = orc.step(p, t0, x, v, reorder=True, binning=True)
+            np.testing.assert_array_equal(kg, ko)
+            np.testing.assert_array_equal(pg, po)
+            np.testing.assert_array_equal(og, oo)
+            np.testing.assert_array_equal(outs[i][0], xo)
+            e = rel_err(outs[i][1], vo, b)
+            assert e.max() <= 1e-12, (i, e.max())
+        else:
+            # reorder step: the output is in (cell, index) order; undo it
+            x1u = np.empty_like(outs[i][0])
+            v1u = np.empty_like(outs[i][1])
+            x1u[:, pg] = outs[i][0]
+            v1u[:, pg] = outs[i][1]
+            xs, vs, _ = orc.stream(p, x, v)
+            d = np.abs(x1u - xs)
+            for k in range(3):
+                d[k] = np.minimum(d[k], b["L"][k] - d[k])
+            assert d.max() < 2e-6, (i, d.max())
+            ko = orc.keys(p, t0, x1u)
+            np.testing.assert_array_equal(kg, ko)
+            po, oo = orc.sort(ko, p.ncells)
+            np.testing.assert_array_equal(pg, po)
+            np.testing.assert_array_equal(og, oo)
+            vo = orc.collide(p, t0, vs, po, oo)
+            e = rel_err(v1u, vo, b)
+            assert e.max() <= 2e-6, (i, e.max())
+
+
 def test_graph_and_direct_launches_agree(mpc):
     """Kernel-by-kernel launches, one-step graphs and graphs of 4 steps (two
     replays plus one single step for 9 steps) give identical results."""
