@@ -229,6 +229,58 @@ def test_batched_parity(mpc):
         assert e.max() <= 1e-12, (i, e.max())
 
 
+@pytest.mark.parametrize("form,walls", [("fp64", False), ("fp64", True), ("fp32", False),
+                                        ("split", False)])
+def test_fast_particles(mpc, form, walls):
+    """k_BT/m = 225 at h = 0.1: particles move 1.5 cells per step on average
+    and up to about 7, so many leave the window of next-step cells around
+    their tile (one histogram atomic each) and, in the 3-cell axis, cross the
+    periodic box more than once (the general wrap).  Between walls (H = 5) the
+    single reflection and the clamp to [0, H] of the streaming rule apply."""
+    L = (3, 9, 5) if walls else (3, 9, 4)
+    box = box_of(L, mbs=True, walls=walls, kT=225.0, seed=51)
+    x, v = synth.box_state(L, kT=225.0, seed=52)
+    t0 = 3
+    print(f"case fast form={form} walls={walls}", flush=True)
+    with mpc.Sim(box, form=form, reorder_every=0) as sim:
+        sim.set_state(x, v)
+        x0, v0 = sim.get_state()
+        sim.set_step(t0)
+        sim.step(1)
+        x1, v1 = sim.get_state()
+        kg, pg, og = sim.get_binning()
+    p = oparams(box)
+    if form == "fp64":
+        xo, vo, ko, po, oo = orc.step(p, t0, x, v, reorder=False, binning=True)
+        moved = np.abs(v0 * box["h"]).max()
+        print(f"largest displacement {moved:.2f} cells")
+        assert moved > 2.0
+        np.testing.assert_array_equal(kg, ko)
+        np.testing.assert_array_equal(pg, po)
+        np.testing.assert_array_equal(og, oo)
+        np.testing.assert_array_equal(x1, xo)
+        e = rel_err(v1, vo, box)
+        report("fast fp64", e)
+        assert e.max() <= 1e-12
+        return
+    xs, vs, _ = orc.stream(p, x0, v0)
+    d = np.abs(x1 - xs)
+    for k in range(3):
+        d[k] = np.minimum(d[k], L[k] - d[k])
+    print(f"{form}: max stream error {d.max():.3e} cells")
+    # FP32: the sum x + h v reaches 16 cells before the wrap; two ulps there
+    assert d.max() < 4e-6
+    ko = orc.keys(p, t0, x1)
+    np.testing.assert_array_equal(kg, ko)
+    po, oo = orc.sort(ko, p.ncells)
+    np.testing.assert_array_equal(pg, po)
+    np.testing.assert_array_equal(og, oo)
+    vo = orc.collide(p, t0, v0, po, oo)
+    e = rel_err(v1, vo, box)
+    report(f"fast {form}", e)
+    assert e.max() <= 2e-6
+
+
 @pytest.mark.parametrize("form", ["fp64", "split"])
 def test_batched_degenerate_boxes(mpc, form):
     """A batch that mixes a single-cell box, boxes one or two cells thick and
