@@ -140,6 +140,9 @@ typedef struct {
                              with v_x -/+ le_u; a collision cell across a z face is
                              formed with the image on the other side, in its velocity
                              frame (with MPC_AMC also with its image positions).
+                             One step takes the offset once, so a particle should
+                             not cross more than one z face per step
+                             (|v_z| dt < L[2] a).
                              0 = plain periodic.  With MPC_WALLS_Z -> MPC_EINVAL  */
 } mpc_params;
 
