@@ -23,7 +23,8 @@ same line carries:
                  (fp64_fixed, walls_slip, walls_couette, lees_edwards,
                  density50, features, reorder_sweep, c5);
   cpu_baseline : the single-threaded CPU oracle on a bounded sample of the
-                 512^3 workload.
+                 512^3 workload (with --cpu-configs also on the 16^3, 256^3,
+                 64-box and channel workloads).
 --copy-probe-gib G adds one torch device-to-device copy of G GiB before the
 run: the counter runs use it to scale FETCH_SIZE / WRITE_SIZE to bytes.
 """
@@ -295,6 +296,40 @@ def cpu_baseline(steps: int = 3):
                       f"workload's cells), plain SRD, FP64, {steps} steps, 1 thread"}
 
 
+def cpu_configs():
+    """The single-threaded FP64 oracle on the other workloads (opt-in, a few
+    minutes): the 16^3 box for all 100 steps; the 256^3 box with the
+    thermostat, the 64-box ensemble and the Poiseuille channel for 5 steps
+    each.  Particle-steps/s per workload, 1 thread."""
+    import oracle
+    import synth
+    out = {}
+
+    def run(name, boxes, steps, kw):
+        states = [synth.box_state(b["L"], density=b["density"], kT=b["kT"], seed=7 + i)
+                  for i, b in enumerate(boxes)]
+        ps = [oracle.Params(L=b["L"], h=b["h"], alpha=b["alpha"], kT=b["kT"],
+                            density=b["density"], seed=b["seed"], mbs=b["mbs"],
+                            walls=b["walls"], g=b["g"], **kw) for b in boxes]
+        n = sum(x.shape[1] for x, _ in states)
+        t0 = time.perf_counter()
+        for t in range(steps):
+            states = [oracle.step(p, t, x, v) for p, (x, v) in zip(ps, states)]
+            if n * steps > 10 ** 8:
+                log(f"[cpu {name}] step {t + 1} of {steps}")
+        wall = time.perf_counter() - t0
+        log(f"[cpu {name}] {n} particles x {steps} steps in {wall:.1f} s")
+        out[name] = {"value": n * steps / wall, "particles": n, "steps": steps,
+                     "seconds": wall}
+        del states
+
+    run("16^3, plain SRD", [synth.config("C1")], 100, {})
+    run("256^3, thermostat", [synth.config("C2")], 5, {})
+    run("64 boxes", synth.batch_boxes(64, seed=4), 5, {})
+    run("256x256x64 channel, walls, gravity, thermostat", [synth.config("C5")], 5, {})
+    return {"unit": "particle-steps/s", "cores": 1, "kind": "oracle", "configs": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,6 +338,9 @@ def main():
     ap.add_argument("--forms", default=DEFAULT_FORMS,
                     help="entries besides the FP64 headline (comma list, or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="also time the CPU oracle on the 16^3, 256^3, 64-box and channel "
+                         "workloads (a few minutes)")
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--c2-steps", type=int, default=200)
     ap.add_argument("--batched-steps", type=int, default=500)
@@ -486,6 +524,8 @@ def main():
         line["copy_probe"] = copy_probe
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
+        if args.cpu_configs:
+            line["cpu_baseline"]["other_workloads"] = cpu_configs()
     print(json.dumps(line), flush=True)
 
 
