@@ -118,6 +118,27 @@ def test_stream_exact_single_rounding(orc):
                 assert min(d, L[k] - d) <= Fraction(2.0**-50) * L[k]
 
 
+def test_stream_wraps_far_outside(orc):
+    """Displacements of many box lengths in one step (Eq. (1) with periodic
+    images): the stored position is the once-rounded x + h v taken modulo L,
+    in [0, L), to a few ulps of L."""
+    L = (3, 2, 5)
+    p = orc.Params(L=L, h=1.0)
+    rng = np.random.default_rng(9)
+    n = 4000
+    x = np.stack([rng.random(n) * L[k] for k in range(3)])
+    v = rng.uniform(-40.0, 40.0, size=(3, n))
+    x2, v2, nb = orc.stream(p, x, v)
+    assert nb == 0 and np.array_equal(v2, v)
+    for k in range(3):
+        assert np.all((x2[k] >= 0.0) & (x2[k] < L[k]))
+        for i in range(n):
+            xe = Fraction(float(Fraction(x[k, i]) + Fraction(v[k, i])))  # one rounding
+            ex = xe - L[k] * math.floor(xe / L[k])
+            d = abs(Fraction(x2[k, i]) - ex)
+            assert min(d, L[k] - d) <= Fraction(2.0**-48) * L[k], (k, i)
+
+
 def test_stream_wrap_corner(orc):
     """A particle landing a hair below 0 maps into [0, L), never onto L."""
     p = orc.Params(L=(4, 4, 4), h=1.0)
