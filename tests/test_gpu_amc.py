@@ -119,6 +119,42 @@ def test_amc_fp64_one_step(mpc, L, density, g, R, t0, mbs):
     assert np.all(e <= tol)
 
 
+def test_amc_batched_boxes(mpc):
+    """SRD+a with the thermostat on a batch of uneven boxes (a single-cell box
+    among them, different angles, temperatures and gravity per box): each box
+    equals its own oracle step, with the cond(I_c) bar."""
+    shapes = [(9, 7, 8), (1, 1, 1), (12, 5, 6), (4, 3, 2)]
+    boxes = [box_of(L, seed=60 + i, mbs=True, alpha=(100.0 + 15.0 * i) * DEG,
+                    kT=0.7 + 0.2 * i, g=(1e-3 * i, 0.0, 0.0)) for i, L in enumerate(shapes)]
+    states = [synth.box_state(b["L"], density=b["density"], kT=b["kT"], seed=300 + i)
+              for i, b in enumerate(boxes)]
+    t0 = 4
+    with mpc.Sim(boxes, form="fp64", reorder_every=5) as sim:
+        for i, (x, v) in enumerate(states):
+            sim.set_state(x, v, box=i)
+        sim.set_step(t0)
+        sim.step(1)
+        outs = [sim.get_state(box=i) for i in range(len(boxes))]
+        bins = [sim.get_binning(box=i) for i in range(len(boxes))]
+    sorted_out = (t0 + 1) % 5 == 0
+    for i, b in enumerate(boxes):
+        x, v = states[i]
+        p = oparams(b)
+        xo, vo, ko, po, oo = orc.step(p, t0, x, v, reorder=sorted_out, binning=True)
+        np.testing.assert_array_equal(bins[i][0], ko)
+        np.testing.assert_array_equal(bins[i][1], po)
+        np.testing.assert_array_equal(bins[i][2], oo)
+        np.testing.assert_array_equal(outs[i][0], xo)
+        xs, _, _ = orc.stream(p, x, v)
+        cond = cell_cond(ko, oo, po, frame(p, t0, xs))
+        if sorted_out:
+            cond = cond[po]
+        e = rel_err(outs[i][1], vo, b)
+        tol = 1e-12 + 64 * EPS * cond
+        print(f"box {i} {b['L']}: max e = {e.max():.3e}, max e/tol = {(e / tol).max():.3f}")
+        assert np.all(e <= tol), i
+
+
 @pytest.mark.parametrize("form,mbs", [("fp32", False), ("split", False), ("fp32", True),
                                       ("split", True)])
 def test_amc_reduced_precision_one_step(mpc, form, mbs):
