@@ -62,6 +62,34 @@ FIXED_CASES = [
 ]
 
 
+def test_fixed_batched_boxes(mpc):
+    """Fixed-point sums with the thermostat on a batch of uneven boxes (a
+    single-cell box among them): each box equals its own oracle step in the
+    same mode."""
+    shapes = [(10, 7, 9), (1, 1, 1), (6, 11, 4)]
+    boxes = [box_of(L, seed=80 + i, mbs=True, kT=0.6 + 0.5 * i) for i, L in enumerate(shapes)]
+    states = [synth.box_state(b["L"], density=b["density"], kT=b["kT"], seed=400 + i)
+              for i, b in enumerate(boxes)]
+    t0 = 2
+    with mpc.Sim(boxes, form="fp64", reorder_every=3) as sim:
+        for i, (x, v) in enumerate(states):
+            sim.set_state(x, v, box=i)
+        sim.set_step(t0)
+        sim.step(1)
+        outs = [sim.get_state(box=i) for i in range(len(boxes))]
+        bins = [sim.get_binning(box=i) for i in range(len(boxes))]
+    for i, b in enumerate(boxes):
+        x, v = states[i]
+        xo, vo, ko, po, oo = orc.step(oparams(b), t0, x, v, reorder=True, binning=True)
+        np.testing.assert_array_equal(bins[i][0], ko)
+        np.testing.assert_array_equal(bins[i][1], po)
+        np.testing.assert_array_equal(bins[i][2], oo)
+        np.testing.assert_array_equal(outs[i][0], xo)
+        e = rel_err(outs[i][1], vo, b)
+        print(f"box {i} {b['L']}: max e = {e.max():.3e}")
+        assert e.max() <= 1e-12, i
+
+
 @pytest.mark.parametrize("L,mbs,walls,amc,g,R,t0", FIXED_CASES)
 def test_fixed_fp64_one_step(mpc, L, mbs, walls, amc, g, R, t0):
     box = box_of(L, seed=3 + t0, mbs=mbs, walls=walls, amc=amc, g=g)
