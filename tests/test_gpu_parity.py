@@ -350,6 +350,25 @@ def test_graph_and_direct_launches_agree(mpc):
         np.testing.assert_array_equal(res[0][1], r[1])
 
 
+def test_batched_graphs_of_k_steps(mpc):
+    """A batch of uneven boxes advanced 9 steps from graphs of 4 steps (two
+    replays and one single step) equals kernel-by-kernel launches, box by box,
+    bit for bit."""
+    boxes = synth.batch_boxes(5, seed=11, lmin=5, lmax=14)
+    states = [synth.box_state(b["L"], density=b["density"], kT=b["kT"], seed=500 + i)
+              for i, b in enumerate(boxes)]
+    res = []
+    for graph in (0, 4):
+        with mpc.Sim(boxes, form="split", reorder_every=3, graph=graph) as sim:
+            for i, (x, v) in enumerate(states):
+                sim.set_state(x, v, box=i)
+            sim.step(9)
+            res.append([sim.get_state(box=i) for i in range(len(boxes))])
+    for a, b in zip(res[0], res[1]):
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+
+
 def test_autotune_keeps_results(mpc):
     """The autotuner restores the state and step counter after its trials, and
     results do not depend on the tiling it picks."""
