@@ -25,6 +25,8 @@ MUTANTS = {
     "stream_dropped_h": ("double xe = fma(h, v[i], x[i]);", "double xe = v[i] + x[i];"),
     "stream_sign": ("double ye = fma(h, v[n + i], x[n + i]);", "double ye = fma(-h, v[n + i], x[n + i]);"),
     "wrap_wrong_branch": ("    x = x + L;\n  } else if (x >= L) {", "    x = x - L;\n  } else if (x >= L) {"),
+    "wrap_far_collapses": ("      x = x - L * floor(x / L);", "      x = 0.0;"),
+    "wrap_far_truncates": ("      x = x - L * floor(x / L);", "      x = x - L * trunc(x / L);"),
     "bounce_keeps_vx": ("v[i] = 2.0 * uw - v[i];", "v[i] = 2.0 * uw + v[i];"),
     "wall_frame_ignored": ("xe = xe - tr2 * (v[i] - uw);", "xe = xe - tr2 * v[i];"),
     "wall_velocity_sign": ("double uw = zw == 0.0 ? -p->uwall : p->uwall;",
@@ -83,6 +85,7 @@ MUTANTS = {
 
 FAST_PINS = [
     "test_uniform_conversions", "test_shift_grid_and_uniformity", "test_stream_wrap_corner",
+    "test_stream_wraps_far_outside",
     "test_stream_exact_single_rounding", "test_bounce_back_walls", "test_keys_exact_floor",
     "test_counting_sort_matches_numpy", "test_rotation_matches_scipy", "test_cell_sums_against_fsum",
     "test_collision_is_rotation_of_relative_velocity", "test_per_cell_momentum_and_energy_conservation",
