@@ -56,6 +56,15 @@ def test_workspace_planning_and_validation_on_host():
     with pytest.raises(m.MPCError) as e:
         m.workspace_bytes(split_big)
     assert e.value.code == m.ERANGE
+    # degenerate inputs: a box whose density rounds to no particle, zero or
+    # negative density, an axis of zero cells
+    for degenerate in (dict(c1, L=(4, 4, 4), density=1e-3), dict(c1, density=0.0),
+                       dict(c1, density=-1.0), dict(c1, L=(16, 0, 16))):
+        with pytest.raises(m.MPCError) as e:
+            m.workspace_bytes(m.make_params(degenerate))
+        assert e.value.code == m.EINVAL
+    # the smallest box: one cell
+    assert m.workspace_bytes(m.make_params(dict(c1, L=(1, 1, 1)))) > 0
     mixed = [m.make_params(c1, "fp64"), m.make_params(c1, "fp32")]
     with pytest.raises(m.MPCError) as e:
         m.workspace_bytes(mixed)
